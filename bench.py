@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled boiling step (flow + temperature) on one MI355X.
+
+Workload: forced-convection boiling on a heated cylinder, 1024x512 channel, cylinder radius 32 at
+x = 256, inlet velocity 0.02 at Re = 300, saturated liquid at T_r = 0.86, superheat 0.1 T_c,
+gravity -1e-5 along x, RK4 temperature stages, FP32 (synthetic initial state: uniform saturated
+liquid).  The configured 3000 warm-up steps (no forcing, no temperature update) run first and
+untimed; the timed steps are full coupled steps.  One lattice update (LUP) = one node (fluid and
+solid) advanced through one full step.
+
+Prints one JSON line: MLUPS, per-step time, the roofline of the dominant kernel (HIP events over
+isolated launches on the library's stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# Algorithmic traffic / work per lattice update of each kernel of the step:
+#   stream+collide: read 9 populations, write 9 populations, read T (psi)       -> 19 values
+#   temperature:    read T^n, write T^{n+1}                                       ->  2 values
+#   temperature useful flops: 4 stages x ~150 + ~130 stage-invariant             -> 730 flops
+KERNEL_NAMES = {0: "k_lbm", 1: "k_thermal"}
+THERMAL_FLOPS_PER_LUP = {4: 730.0, 2: 430.0}
+PREC = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+STORE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
+COMPUTE_BYTES = {0: 8, 1: 4, 2: 4, 3: 4}
+
+
+def kernel_bytes_per_lup(kernel: int, prec: int) -> float:
+    if kernel == 0:
+        return 18 * STORE_BYTES[prec] + COMPUTE_BYTES[prec]
+    return 2 * COMPUTE_BYTES[prec]
+
+
+def source_digest() -> str:
+    p = os.path.join(ROOT, "paper_1912_02018_amd", "csrc", "lbm_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p)).get(f"{kernel_name}@{workload}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """FP64 oracle (OpenMP over nodes) on the same workload, timed on a bounded number of steps."""
+    import oracle
+    from paper_1912_02018_amd.config import FP64
+    c = cfg.replace(precision=FP64, warmup_steps=0)
+    sim = oracle.Sim(c)
+    t0 = time.perf_counter()
+    sim.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, min(200, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    sim.step(n)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(c.nx * c.ny * n / dt / 1e6, 4), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} coupled FP64 steps of the {c.nx}x{c.ny} workload after 1 untimed step "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--precision", default="f32", choices=sorted(PREC))
+    ap.add_argument("--kernel-launches", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the boiling step is not split across GPUs in this build "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_02018_amd import lbm
+    from paper_1912_02018_amd.config import config2
+
+    prec = PREC[args.precision]
+    cfg = config2(prec)
+    workload = f"boiling-cylinder-{cfg.nx}x{cfg.ny}-R{cfg.cyl_r}-Re300-rk{cfg.rk_stages}"
+    torch.cuda.set_device(0)
+    sim = lbm.Simulation(cfg)
+    stream = sim.stream
+    sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    nodes = cfg.nx * cfg.ny
+    mlups = nodes / (ms_step * 1e-3) / 1e6
+
+    mass = sim.total_mass()
+    q, nu, nu_avg = sim.wall_heat_flux()
+    if not (mass == mass and nu == nu):
+        print("non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(3)
+
+    # isolated launches of each kernel of the step, timed with HIP events on the same stream
+    kt = {}
+    for k in (0, 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        sim.time_kernel(k, 10)
+        e0.record(stream)
+        sim.time_kernel(k, args.kernel_launches)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kt[k] = e0.elapsed_time(e1) / args.kernel_launches  # ms per launch
+    dom = max(kt, key=kt.get)
+    name = KERNEL_NAMES[dom]
+    if dom == 0:
+        per_launch = kernel_bytes_per_lup(0, prec) * nodes
+        achieved = per_launch / (kt[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload)}
+    else:
+        flops = THERMAL_FLOPS_PER_LUP[cfg.rk_stages] * nodes
+        achieved = flops / (kt[dom] * 1e-3) / 1e12
+        peak = FP64_VECTOR_PEAK_TFLOPS if prec == 0 else FP32_VECTOR_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(name, workload)}
+    roof["kernel"] = name
+    roof["kernel_ms"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in kt.items()}
+    roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
+                              for k, v in kt.items()}
+
+    line = {
+        "metric": "MLUPS (flow+thermal) & % HBM peak; batched vs single & FP16-store vs FP32 at error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f64", 1: "f32", 2: "f16-store/f32", 3: "bf16-store/f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r,
+                   "u_in": cfg.u_in, "Re": 300, "rk_stages": cfg.rk_stages,
+                   "warmup_steps_untimed": cfg.warmup_steps + args.warmup, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "wall_s": round(wall, 3),
+        "diagnostics": {"mass": mass, "q_mean": q, "nu": nu},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

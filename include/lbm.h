@@ -1,0 +1,153 @@
+/*
+ * lbm.h -- C ABI of liblbm, an MI355X (gfx950) implementation of one coupled time step of the
+ * central-moment pseudopotential lattice Boltzmann method for forced-convection boiling on a
+ * heated cylinder (Saito et al., "Lattice Boltzmann modeling and simulation of forced-convection
+ * boiling on a cylinder", arXiv:1912.02018).
+ *
+ * One step of a run (Sec. II of the paper) is
+ *   streaming of the post-collision populations (eq. streaming) with the velocity inlet, the
+ *   convective outlet and the interpolated bounce-back cylinder (Sec. IV A);
+ *   density and momentum (Sec. II A); pseudopotential psi(rho, T) from the Peng-Robinson EOS
+ *   (eq. potential, eq. eos); the 24-neighbour interaction force (eq. interForce) plus gravity;
+ *   the central-moment collision with consistent forcing and the thermodynamic-consistency
+ *   terms (eq. postColl2), reconstructed as f* = M^-1 N(-u) k* (Appendix A);
+ *   the finite-difference temperature equation (eq. energy) with Runge-Kutta stages, third-order
+ *   upwind convection and the isotropic gradient/Laplacian of the interaction stencil;
+ *   FP64 reductions of the total mass and of the wall heat flux / Nusselt number (Sec. IV B).
+ *
+ * Conventions
+ *   * Fields are row-major [ny][nx] (x fastest); node (x, y) has index y*nx + x.  Populations
+ *     follow the paper's velocity order c_x = {0,1,-1,0,0,1,-1,1,-1}, c_y = {0,0,0,1,-1,1,-1,-1,1}.
+ *   * The state of a run after n steps is: the post-collision populations f* of step n-1, the
+ *     post-streaming populations 2, 6, 8 of the last column from step n-1 (outlet history) and
+ *     the temperature T^n.  Density and velocity are derived by streaming (lbm_fields).
+ *   * The caller owns the device workspace (size from lbm_workspace_bytes, 256-byte aligned)
+ *     and the HIP stream; both must outlive the handle.  The library allocates no device memory.
+ *     Every device action is enqueued on that stream; only calls that return host data wait for
+ *     it.  Host pointers belong to the caller and are not retained.
+ *   * Errors are negative return codes; lbm_last_error() gives a message.  A handle is not
+ *     thread-safe; calls on one handle must not overlap.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_handle lbm_handle;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument or configuration */
+    LBM_ENOMEM = -2,    /* workspace too small */
+    LBM_EDEVICE = -3,   /* a HIP call failed */
+    LBM_EUNSTABLE = -4, /* non-finite state detected (e.g. negative psi radicand, blow-up) */
+    LBM_ESTATE = -5     /* call not valid in the handle's state */
+};
+
+/* arithmetic of the step: FP64; FP32; FP32 compute with populations stored as FP16 or BF16
+ * holding f_i - w_i * rho_ref_shift (temperature and macroscopic fields stay FP32) */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_BF16S = 3 };
+
+/* x boundaries; y is always periodic */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_INLET_OUTLET = 1 };
+
+typedef struct {
+    int32_t nx, ny;         /* grid (>= 4 each) */
+    int32_t bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INLET_OUTLET */
+    int32_t rk_stages;      /* temperature update: 0 none, 2 Heun, 4 classical RK4 */
+    int32_t warmup_steps;   /* first steps with neither forcing nor temperature update (Sec. IV A) */
+    int32_t cyl_x, cyl_y, cyl_r; /* cylinder centre / radius in lattice units; cyl_r <= 0: none.
+                                    Solid nodes: (x-cyl_x)^2 + (y-cyl_y)^2 <= cyl_r^2.  The
+                                    cylinder must keep 3 nodes from the x ends and 2 from y. */
+    int32_t upwind_kind;    /* 0: third-order upwind (dissipation 1/12), 1: Kawamura-Kuwahara (1/4) */
+    int32_t diag_every;     /* > 0: accumulate Nu of the state every diag_every steps */
+    double nu;              /* kinematic viscosity; omega = (nu/cs^2 + 1/2)^-1 (Sec. II A) */
+    double eos_a, eos_b, eos_R, acentric; /* Peng-Robinson constants (eq. eos) */
+    double Tr_sat;          /* saturation temperature / T_c, T_c = 0.0778 a / (0.4572 b R) */
+    double dTr_wall;        /* wall superheat / T_c */
+    double G, sigma;        /* interaction sign/strength (eq. potential), consistency constant */
+    double gx, gy;          /* gravity: body force (rho - rho_gref) g */
+    double rho_gref;        /* < 0 selects rho_l */
+    double rho_l, rho_v;    /* coexistence densities; both <= 0: Maxwell construction at T_sat */
+    double rho_wall;        /* density of solid nodes for psi; <= 0 selects rho_l */
+    double u_in;            /* inlet velocity (also the outlet convection speed) */
+    double alpha_T;         /* thermal diffusivity */
+    double cv;              /* specific heat at constant volume */
+    int32_t precision;      /* LBM_FP64 ... LBM_BF16S; all runs of a handle share it */
+    int32_t check_every;    /* > 0: lbm_step checks the state for non-finite values */
+    double rho_ref_shift;   /* reduced-precision storage offset rho_ref (f_i - w_i rho_ref) */
+} lbm_config;
+
+/* Bytes of device workspace needed for n_runs runs (cfgs[0..n_runs-1]); 0 on invalid input. */
+size_t lbm_workspace_bytes(const lbm_config *cfgs, int n_runs);
+
+/* Create a handle for n_runs runs stepped together.  Copies the configs, derives the constants,
+ * carves dev_workspace and initialises every run to its default state: saturated liquid
+ * (rho_l) moving with (u_in, 0) at T_sat, solid nodes at T_w (Sec. IV A).  hip_stream is a
+ * hipStream_t (NULL: default stream).  On error *out is NULL. */
+int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes,
+               void *hip_stream, lbm_handle **out);
+
+/* Advance every run by n_steps coupled steps (asynchronous unless check_every > 0, in which
+ * case the call waits at its end and returns LBM_EUNSTABLE if a check failed). */
+int lbm_step(lbm_handle *h, int n_steps);
+
+/* Host copies of the macroscopic fields of the current state of one run: rho, u = (j + F/2)/rho,
+ * T; solid nodes report rho = 0, u = 0, T = T_w and mask = 1.  Each pointer may be NULL.
+ * Waits for the stream. */
+int lbm_fields(lbm_handle *h, int run, double *rho, double *ux, double *uy, double *T,
+               uint8_t *solid_mask);
+
+/* Set a run's state from host fields: f* := f^eq(rho, u) (full Hermite, eq. equi) at every node,
+ * outlet history := f^eq of the last column, T := T (NULL: T_sat), solid T := T_w.  Resets the
+ * step counter of the handle and the Nu accumulators of the run.  Waits for the stream. */
+int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy,
+                   const double *T);
+
+/* Raw state of one run as FP64 host copies: fstar [9][ny][nx] (values at solid nodes are
+ * unspecified), hist [3][ny] (populations 2, 6, 8), T [ny][nx].  Each pointer may be NULL. */
+int lbm_get_state(lbm_handle *h, int run, double *fstar, double *hist, double *T);
+
+/* Replace the raw state of one run (converted to the storage precision) and set the step
+ * counter of the handle to `step`. */
+int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *hist,
+                  const double *T, int64_t step);
+
+/* Wall heat flux of the current state (Sec. IV B): N_p = 8 ceil(pi R / 4) probes at radius
+ * R + 1.5, q_p = rho_p c_v alpha (T_w - T_p) / 1.5 with bilinear rho_p, T_p; q_mean is their
+ * mean, nu = q_mean 2R / (rho_v c_v alpha dT); nu_time_avg is the mean of the Nu values
+ * accumulated during lbm_step (0 if none).  FP64.  Waits for the stream. */
+int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, double *nu_time_avg);
+
+/* FP64 sum of rho over the fluid nodes of the current state.  Waits for the stream. */
+int lbm_total_mass(lbm_handle *h, int run, double *mass);
+
+/* Derived constants of a run: [Tc, T_sat, T_w, rho_l, rho_v, rho_w, rho_gref, omega]. */
+int lbm_derived(lbm_handle *h, int run, double *out8);
+
+/* Timing hook: enqueue n_launches back-to-back launches of one kernel of the step on the current
+ * state of every run, without advancing it (the kernels write only the spare buffers and the
+ * macroscopic fields of the current state).  kernel: 0 = streaming + collision (k_lbm),
+ * 1 = temperature update (k_thermal; every run must have rk_stages > 0).  Asynchronous. */
+enum { LBM_KERNEL_STREAM_COLLIDE = 0, LBM_KERNEL_THERMAL = 1 };
+int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
+
+/* Steps taken since creation / the last set_fields / set_state. */
+int64_t lbm_step_count(const lbm_handle *h);
+
+/* Message of the last error on this handle (or of the last failed lbm_create if h is NULL). */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Release the handle (does not free the caller's workspace; waits for the stream). */
+void lbm_destroy(lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,646 @@
+// Host side of the C ABI declared in include/lbm.h: configuration checks, derived constants,
+// workspace carving, launch sequencing and host read-back.  All device work is enqueued on the
+// caller's stream; the library never allocates device memory.
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using lbm::RunDev;
+using lbm::Tile;
+
+struct lbm_handle {
+    int n_runs = 0;
+    int precision = 0;
+    int rk = 0;
+    hipStream_t stream = nullptr;
+    std::vector<lbm_config> cfgs;
+    std::vector<RunDev> runs;         // host copies of the device descriptors
+    RunDev *runs_dev = nullptr;
+    Tile *tiles_lbm = nullptr, *tiles_th = nullptr;
+    std::vector<int> lbm_off, lbm_cnt, th_off, th_cnt;
+    int n_lbm = 0, n_th = 0;
+    int pf = 0, pt = 0, ph = 0;
+    long long step = 0;
+    std::string err;
+};
+
+namespace {
+
+std::string g_create_error;
+
+int fail(lbm_handle *h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(h, LBM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+size_t storage_bytes(int precision) { return precision == 0 ? 8 : (precision == 1 ? 4 : 2); }
+size_t compute_bytes(int precision) { return precision == 0 ? 8 : 4; }
+int probe_count(int r) { return r > 0 ? 8 * (int)std::ceil(M_PI * r / 4.0) : 0; }
+
+// ---- Peng-Robinson thermodynamics on the host (set-up only) -----------------------------------
+struct PR {
+    double a, b, R, kappa, Tc;
+    explicit PR(const lbm_config &c)
+        : a(c.eos_a), b(c.eos_b), R(c.eos_R),
+          kappa(0.37464 + 1.54226 * c.acentric - 0.26992 * c.acentric * c.acentric),
+          Tc(0.0778 * c.eos_a / (0.4572 * c.eos_b * c.eos_R)) {}
+    double phi(double T) const { double s = 1.0 + kappa * (1.0 - std::sqrt(T / Tc)); return s * s; }
+    // pressure as a function of specific volume v = 1/rho
+    double p_v(double v, double T) const { return R * T / (v - b) - a * phi(T) / (v * v + 2.0 * b * v - b * b); }
+    double dp_dv(double v, double T) const
+    {
+        double d = v * v + 2.0 * b * v - b * b;
+        return -R * T / ((v - b) * (v - b)) + a * phi(T) * (2.0 * v + 2.0 * b) / (d * d);
+    }
+    // integral of p dv
+    double P_int(double v, double T) const
+    {
+        double s2 = std::sqrt(2.0);
+        return R * T * std::log(v - b) - a * phi(T) / (2.0 * s2 * b) * std::log((v + b - s2 * b) / (v + b + s2 * b));
+    }
+};
+
+// Maxwell construction: equal area under the isotherm p(v) between the liquid and vapour
+// volumes.  The two spinodal volumes bracket the loop; for a trial pressure the outer roots are
+// found by bisection on the monotone branches and the pressure is adjusted by bisection until
+// the area between the isotherm and the horizontal line vanishes.
+bool maxwell(const PR &pr, double T, double &rho_v, double &rho_l)
+{
+    const double vmin = pr.b * 1.000001, vmax = 1e6;
+    // spinodals: sign changes of dp/dv on a logarithmic scan of v
+    std::vector<double> sp;
+    const int N = 40000;
+    double lv0 = std::log(vmin), lv1 = std::log(vmax);
+    double prev_v = vmin, prev_d = pr.dp_dv(vmin, T);
+    for (int k = 1; k <= N && sp.size() < 2; ++k) {
+        double v = std::exp(lv0 + (lv1 - lv0) * k / N);
+        double d = pr.dp_dv(v, T);
+        if ((d > 0) != (prev_d > 0)) {
+            double lo = prev_v, hi = v, dlo = prev_d;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi), dm = pr.dp_dv(mid, T);
+                if ((dm > 0) == (dlo > 0)) { lo = mid; dlo = dm; } else hi = mid;
+            }
+            sp.push_back(0.5 * (lo + hi));
+        }
+        prev_v = v;
+        prev_d = d;
+    }
+    if (sp.size() < 2) return false;
+    const double v_sl = sp[0], v_sv = sp[1];  // liquid spinodal (smaller v), vapour spinodal
+    double plo = std::max(pr.p_v(v_sl, T), 1e-14), phi_ = pr.p_v(v_sv, T);
+    auto root = [&](double p, double lo, double hi) {
+        double flo = pr.p_v(lo, T) - p;
+        for (int it = 0; it < 300; ++it) {
+            double mid = 0.5 * (lo + hi), fm = pr.p_v(mid, T) - p;
+            if ((fm > 0) == (flo > 0)) { lo = mid; flo = fm; } else hi = mid;
+        }
+        return 0.5 * (lo + hi);
+    };
+    double vl = 0, vv = 0;
+    for (int it = 0; it < 200; ++it) {
+        double p = 0.5 * (plo + phi_);
+        vl = root(p, vmin, v_sl);
+        vv = root(p, v_sv, vmax);
+        double area = pr.P_int(vv, T) - pr.P_int(vl, T) - p * (vv - vl);
+        if (area > 0) plo = p; else phi_ = p;
+    }
+    rho_l = 1.0 / vl;
+    rho_v = 1.0 / vv;
+    return true;
+}
+
+int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
+{
+    if (!c || n <= 0) return fail(h, LBM_EINVAL, "no run configurations");
+    for (int r = 0; r < n; ++r) {
+        const lbm_config &k = c[r];
+        if (k.nx < 4 || k.ny < 4) return fail(h, LBM_EINVAL, "run %d: grid must be at least 4x4", r);
+        if ((long long)k.nx * k.ny > (1LL << 31)) return fail(h, LBM_EINVAL, "run %d: grid too large", r);
+        if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET) return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
+        if (k.precision < 0 || k.precision > 3) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
+        if (k.precision != c[0].precision) return fail(h, LBM_EINVAL, "all runs must share one precision");
+        if (k.rk_stages != 0 && k.rk_stages != 2 && k.rk_stages != 4) return fail(h, LBM_EINVAL, "run %d: rk_stages must be 0, 2 or 4", r);
+        if (k.rk_stages != c[0].rk_stages) return fail(h, LBM_EINVAL, "all runs must share rk_stages");
+        if (!(k.nu > 0)) return fail(h, LBM_EINVAL, "run %d: nu must be positive", r);
+        if (k.G == 0) return fail(h, LBM_EINVAL, "run %d: G must be nonzero", r);
+        if (k.rk_stages > 0 && !(k.cv > 0 && k.alpha_T >= 0)) return fail(h, LBM_EINVAL, "run %d: bad thermal constants", r);
+        if (!(k.eos_a > 0 && k.eos_b > 0 && k.eos_R > 0 && k.Tr_sat > 0)) return fail(h, LBM_EINVAL, "run %d: bad EOS constants", r);
+        if (k.warmup_steps < 0 || k.diag_every < 0 || k.check_every < 0) return fail(h, LBM_EINVAL, "run %d: negative counter", r);
+        if (k.cyl_r > 0) {
+            if (k.cyl_x - k.cyl_r < 3 || k.cyl_x + k.cyl_r > k.nx - 4 || k.cyl_y - k.cyl_r < 2 || k.cyl_y + k.cyl_r > k.ny - 3)
+                return fail(h, LBM_EINVAL, "run %d: cylinder too close to the domain edge", r);
+            if (probe_count(k.cyl_r) > lbm::kMaxProbes) return fail(h, LBM_EINVAL, "run %d: cylinder too large", r);
+        }
+    }
+    *prec = c[0].precision;
+    *rk = c[0].rk_stages;
+    return LBM_OK;
+}
+
+struct Layout {
+    size_t runs_off, tiles_lbm_off, tiles_th_off, total;
+    std::vector<size_t> run_off;
+    int n_lbm, n_th;
+};
+
+size_t run_bytes(const lbm_config &k)
+{
+    const size_t plane = (size_t)k.ny * pitch_of(k.nx);
+    const size_t sb = storage_bytes(k.precision), cb = compute_bytes(k.precision);
+    size_t b = 0;
+    b += 2 * align256(9 * plane * sb);                      // f[2]
+    b += 5 * align256(plane * cb);                          // T[2], rho, ux, uy
+    b += 2 * align256(3 * (size_t)k.ny * cb);               // hist[2]
+    b += align256(2 * sizeof(double) * std::max(1, probe_count(k.cyl_r)));  // probes
+    b += align256(sizeof(double) * lbm::kDiagBlocks);       // partials
+    b += align256(sizeof(double) * 8);                      // acc
+    return b;
+}
+
+Layout layout(const lbm_config *c, int n)
+{
+    Layout L;
+    const lbm::TileShape ts = lbm::tile_shape(c[0].precision, c[0].rk_stages);
+    L.n_lbm = L.n_th = 0;
+    for (int r = 0; r < n; ++r) {
+        L.n_lbm += ((c[r].nx + ts.lbm_tx - 1) / ts.lbm_tx) * ((c[r].ny + ts.lbm_ty - 1) / ts.lbm_ty);
+        L.n_th += ((c[r].nx + ts.th_tx - 1) / ts.th_tx) * ((c[r].ny + ts.th_ty - 1) / ts.th_ty);
+    }
+    size_t off = 0;
+    L.runs_off = off; off += align256(sizeof(RunDev) * n);
+    L.tiles_lbm_off = off; off += align256(sizeof(Tile) * L.n_lbm);
+    L.tiles_th_off = off; off += align256(sizeof(Tile) * L.n_th);
+    for (int r = 0; r < n; ++r) { L.run_off.push_back(off); off += run_bytes(c[r]); }
+    L.total = off;
+    return L;
+}
+
+double ld_storage(const unsigned char *p, int prec, size_t k)
+{
+    switch (prec) {
+    case 0: return ((const double *)p)[k];
+    case 1: return ((const float *)p)[k];
+    case 2: return (double)__half2float(((const __half *)p)[k]);
+    default: return (double)__bfloat162float(((const __hip_bfloat16 *)p)[k]);
+    }
+}
+
+void st_storage(unsigned char *p, int prec, size_t k, double v)
+{
+    switch (prec) {
+    case 0: ((double *)p)[k] = v; break;
+    case 1: ((float *)p)[k] = (float)v; break;
+    case 2: ((__half *)p)[k] = __float2half_rn((float)v); break;
+    default: ((__hip_bfloat16 *)p)[k] = __float2bfloat16((float)v); break;
+    }
+}
+
+double ld_compute(const unsigned char *p, int prec, size_t k)
+{
+    return prec == 0 ? ((const double *)p)[k] : (double)((const float *)p)[k];
+}
+
+void st_compute(unsigned char *p, int prec, size_t k, double v)
+{
+    if (prec == 0) ((double *)p)[k] = v;
+    else ((float *)p)[k] = (float)v;
+}
+
+const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+bool solid_host(const RunDev &R, int x, int y)
+{
+    if (R.cyl_r <= 0) return false;
+    long dx = x - R.cyl_x, dy = y - R.cyl_y;
+    return dx * dx + dy * dy <= (long)R.cyl_r * R.cyl_r;
+}
+
+int check_run(lbm_handle *h, int run)
+{
+    if (!h) return LBM_EINVAL;
+    if (run < 0 || run >= h->n_runs) return fail(h, LBM_EINVAL, "run index %d out of range", run);
+    return LBM_OK;
+}
+
+// upload host fields (double, [ny][nx]) into a pitched compute-type plane
+int upload_plane(lbm_handle *h, const RunDev &R, void *dst, const double *src, double fill)
+{
+    const size_t cb = compute_bytes(h->precision);
+    std::vector<unsigned char> buf((size_t)R.ny * R.pitch * cb, 0);
+    for (int y = 0; y < R.ny; ++y)
+        for (int x = 0; x < R.nx; ++x)
+            st_compute(buf.data(), h->precision, (size_t)y * R.pitch + x, src ? src[(size_t)y * R.nx + x] : fill);
+    HIPCHK(h, hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int download_plane(lbm_handle *h, const RunDev &R, const void *src, std::vector<double> &out)
+{
+    const size_t cb = compute_bytes(h->precision);
+    std::vector<unsigned char> buf((size_t)R.ny * R.pitch * cb);
+    HIPCHK(h, hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out.resize((size_t)R.nx * R.ny);
+    for (int y = 0; y < R.ny; ++y)
+        for (int x = 0; x < R.nx; ++x) out[(size_t)y * R.nx + x] = ld_compute(buf.data(), h->precision, (size_t)y * R.pitch + x);
+    return LBM_OK;
+}
+
+// macroscopic pass of one run without collision (writes rho, ux, uy of the current state)
+int moments_pass(lbm_handle *h, int run)
+{
+    HIPCHK(h, lbm::launch_lbm(h->precision, false, h->runs_dev, h->tiles_lbm + h->lbm_off[run], h->lbm_cnt[run],
+                              h->pf, h->pt, h->ph, h->step, h->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_config *cfgs, int n_runs)
+{
+    int prec, rk;
+    if (validate(cfgs, n_runs, &prec, &rk, nullptr) != LBM_OK) return 0;
+    return layout(cfgs, n_runs).total;
+}
+
+int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+               lbm_handle **out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int prec, rk;
+    int rc = validate(cfgs, n_runs, &prec, &rk, nullptr);
+    if (rc != LBM_OK) return rc;
+    const Layout L = layout(cfgs, n_runs);
+    if (!dev_workspace || ws_bytes < L.total) return fail(nullptr, LBM_ENOMEM, "workspace needs %zu bytes", L.total);
+    if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+
+    lbm_handle *h = new lbm_handle();
+    h->n_runs = n_runs;
+    h->precision = prec;
+    h->rk = rk;
+    h->stream = (hipStream_t)hip_stream;
+    h->cfgs.assign(cfgs, cfgs + n_runs);
+    unsigned char *ws = (unsigned char *)dev_workspace;
+    h->runs_dev = (RunDev *)(ws + L.runs_off);
+    h->tiles_lbm = (Tile *)(ws + L.tiles_lbm_off);
+    h->tiles_th = (Tile *)(ws + L.tiles_th_off);
+    const lbm::TileShape ts = lbm::tile_shape(prec, rk);
+    std::vector<Tile> tl, tt;
+    std::vector<std::vector<double>> probes(n_runs);
+
+    for (int r = 0; r < n_runs; ++r) {
+        const lbm_config &k = cfgs[r];
+        RunDev R;
+        std::memset(&R, 0, sizeof(R));
+        R.nx = k.nx; R.ny = k.ny; R.pitch = pitch_of(k.nx); R.bc_x = k.bc_x;
+        R.cyl_x = k.cyl_x; R.cyl_y = k.cyl_y; R.cyl_r = k.cyl_r;
+        R.rk = k.rk_stages; R.upwind_kind = k.upwind_kind; R.warmup = k.warmup_steps;
+        R.np = probe_count(k.cyl_r);
+        PR pr(k);
+        R.Tc = pr.Tc;
+        R.kappa = pr.kappa;
+        R.T_sat = k.Tr_sat * pr.Tc;
+        R.T_w = R.T_sat + k.dTr_wall * pr.Tc;
+        double rl = k.rho_l, rv = k.rho_v;
+        if (rl <= 0 || rv <= 0) {
+            if (!maxwell(pr, R.T_sat, rv, rl)) {
+                delete h;
+                return fail(nullptr, LBM_EINVAL, "run %d: no liquid-vapour coexistence at T_sat", r);
+            }
+        }
+        R.rho_l = rl; R.rho_v = rv;
+        R.rho_w = k.rho_wall > 0 ? k.rho_wall : rl;
+        R.rho_gref = k.rho_gref >= 0 ? k.rho_gref : rl;
+        R.omega = 1.0 / (k.nu / (1.0 / 3.0) + 0.5);
+        R.sigma = k.sigma; R.G = k.G; R.gx = k.gx; R.gy = k.gy;
+        R.eos_a = k.eos_a; R.eos_b = k.eos_b; R.eos_R = k.eos_R;
+        R.u_in = k.u_in; R.alpha = k.alpha_T; R.cv = k.cv;
+        R.shift = prec >= 2 ? k.rho_ref_shift : 0.0;
+
+        unsigned char *p = ws + L.run_off[r];
+        const size_t plane = (size_t)R.ny * R.pitch;
+        const size_t sb = storage_bytes(prec), cb = compute_bytes(prec);
+        for (int b = 0; b < 2; ++b) { R.f[b] = p; p += align256(9 * plane * sb); }
+        for (int b = 0; b < 2; ++b) { R.T[b] = p; p += align256(plane * cb); }
+        R.rho = p; p += align256(plane * cb);
+        R.ux = p; p += align256(plane * cb);
+        R.uy = p; p += align256(plane * cb);
+        for (int b = 0; b < 2; ++b) { R.hist[b] = p; p += align256(3 * (size_t)R.ny * cb); }
+        R.probes = (const double *)p; p += align256(2 * sizeof(double) * std::max(1, R.np));
+        R.partials = (double *)p; p += align256(sizeof(double) * lbm::kDiagBlocks);
+        R.acc = (double *)p; p += align256(sizeof(double) * 8);
+        h->runs.push_back(R);
+
+        // probe ring at radius R + 1.5
+        probes[r].resize(2 * std::max(1, R.np));
+        for (int q = 0; q < R.np; ++q) {
+            double th = 2.0 * M_PI * (q + 0.5) / R.np, rr = R.cyl_r + 1.5;
+            probes[r][2 * q] = R.cyl_x + rr * std::cos(th);
+            probes[r][2 * q + 1] = R.cyl_y + rr * std::sin(th);
+        }
+        // tiles
+        h->lbm_off.push_back((int)tl.size());
+        for (int ty = 0; ty < (R.ny + ts.lbm_ty - 1) / ts.lbm_ty; ++ty)
+            for (int tx = 0; tx < (R.nx + ts.lbm_tx - 1) / ts.lbm_tx; ++tx) tl.push_back(Tile{r, tx, ty, 0});
+        h->lbm_cnt.push_back((int)tl.size() - h->lbm_off.back());
+        h->th_off.push_back((int)tt.size());
+        for (int ty = 0; ty < (R.ny + ts.th_ty - 1) / ts.th_ty; ++ty)
+            for (int tx = 0; tx < (R.nx + ts.th_tx - 1) / ts.th_tx; ++tx) tt.push_back(Tile{r, tx, ty, 0});
+        h->th_cnt.push_back((int)tt.size() - h->th_off.back());
+    }
+    h->n_lbm = (int)tl.size();
+    h->n_th = (int)tt.size();
+
+    auto upload = [&](void *dst, const void *src, size_t bytes) -> int {
+        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+        return LBM_OK;
+    };
+    if ((rc = upload(h->runs_dev, h->runs.data(), sizeof(RunDev) * n_runs)) ||
+        (rc = upload(h->tiles_lbm, tl.data(), sizeof(Tile) * tl.size())) ||
+        (rc = upload(h->tiles_th, tt.data(), sizeof(Tile) * tt.size()))) {
+        g_create_error = h->err;
+        delete h;
+        return rc;
+    }
+    for (int r = 0; r < n_runs; ++r) {
+        if ((rc = upload((void *)h->runs[r].probes, probes[r].data(), sizeof(double) * probes[r].size()))) {
+            g_create_error = h->err;
+            delete h;
+            return rc;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(nullptr, LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    // default state of every run: saturated liquid moving with the inlet velocity at T_sat
+    for (int r = 0; r < n_runs; ++r) {
+        const RunDev &R = h->runs[r];
+        std::vector<double> rho((size_t)R.nx * R.ny, R.rho_l), ux(rho.size(), R.bc_x == 1 ? cfgs[r].u_in : 0.0),
+            uy(rho.size(), 0.0);
+        if ((rc = lbm_set_fields(h, r, rho.data(), ux.data(), uy.data(), nullptr)) != LBM_OK) {
+            g_create_error = h->err;
+            delete h;
+            return rc;
+        }
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy, const double *T)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!rho || !ux || !uy) return fail(h, LBM_EINVAL, "rho, ux and uy are required");
+    // make the target buffers the current ones of every run: bring other runs along by copying
+    if (h->pf != 0 || h->pt != 0 || h->ph != 0) {
+        for (int r = 0; r < h->n_runs; ++r) {
+            const RunDev &R = h->runs[r];
+            const size_t plane = (size_t)R.ny * R.pitch;
+            if (h->pf) HIPCHK(h, hipMemcpyAsync(R.f[0], R.f[1], 9 * plane * storage_bytes(h->precision), hipMemcpyDeviceToDevice, h->stream));
+            if (h->pt) HIPCHK(h, hipMemcpyAsync(R.T[0], R.T[1], plane * compute_bytes(h->precision), hipMemcpyDeviceToDevice, h->stream));
+            if (h->ph) HIPCHK(h, hipMemcpyAsync(R.hist[0], R.hist[1], 3 * (size_t)R.ny * compute_bytes(h->precision), hipMemcpyDeviceToDevice, h->stream));
+        }
+        h->pf = h->pt = h->ph = 0;
+    }
+    const RunDev &R = h->runs[run];
+    if ((rc = upload_plane(h, R, R.rho, rho, 0)) || (rc = upload_plane(h, R, R.ux, ux, 0)) ||
+        (rc = upload_plane(h, R, R.uy, uy, 0)) || (rc = upload_plane(h, R, R.T[0], T, R.T_sat)))
+        return rc;
+    HIPCHK(h, hipMemsetAsync(R.acc, 0, sizeof(double) * 8, h->stream));
+    HIPCHK(h, lbm::launch_init(h->precision, h->runs_dev, run, R, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->step = 0;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle *h, int n_steps)
+{
+    if (!h) return LBM_EINVAL;
+    if (n_steps < 0) return fail(h, LBM_EINVAL, "negative step count");
+    bool any_check = false;
+    for (int r = 0; r < h->n_runs; ++r) any_check |= h->cfgs[r].check_every > 0;
+    for (int s = 0; s < n_steps; ++s) {
+        HIPCHK(h, lbm::launch_lbm(h->precision, true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph, h->step,
+                                  h->stream));
+        bool thermal = false;
+        for (int r = 0; r < h->n_runs; ++r) {
+            const lbm_config &k = h->cfgs[r];
+            const bool fon = h->step >= k.warmup_steps;
+            const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
+            const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
+            if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->runs[r], h->pt, acc ? 1 : 0, h->stream));
+            thermal |= fon && k.rk_stages > 0;
+        }
+        if (thermal) {
+            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step, h->stream));
+            h->pt ^= 1;
+        }
+        h->pf ^= 1;
+        h->ph ^= 1;
+        h->step += 1;
+    }
+    if (any_check) {
+        for (int r = 0; r < h->n_runs; ++r) {
+            double acc[8];
+            HIPCHK(h, hipMemcpyAsync(acc, h->runs[r].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            if (acc[5] != 0.0) return fail(h, LBM_EUNSTABLE, "run %d: non-finite state detected", r);
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_fields(lbm_handle *h, int run, double *rho, double *ux, double *uy, double *T, uint8_t *mask)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    const RunDev &R = h->runs[run];
+    if ((rc = moments_pass(h, run))) return rc;
+    std::vector<double> buf;
+    struct { void *src; double *dst; bool zero_solid; } outs[4] = {
+        {R.rho, rho, true}, {R.ux, ux, true}, {R.uy, uy, true}, {R.T[h->pt], T, false}};
+    for (auto &o : outs) {
+        if (!o.dst) continue;
+        if ((rc = download_plane(h, R, o.src, buf))) return rc;
+        for (int y = 0; y < R.ny; ++y)
+            for (int x = 0; x < R.nx; ++x) {
+                const size_t k = (size_t)y * R.nx + x;
+                o.dst[k] = (o.zero_solid && solid_host(R, x, y)) ? 0.0 : buf[k];
+            }
+    }
+    if (mask)
+        for (int y = 0; y < R.ny; ++y)
+            for (int x = 0; x < R.nx; ++x) mask[(size_t)y * R.nx + x] = solid_host(R, x, y) ? 1 : 0;
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_handle *h, int run, double *fstar, double *hist, double *T)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    const RunDev &R = h->runs[run];
+    const size_t plane = (size_t)R.ny * R.pitch;
+    if (fstar) {
+        const size_t sb = storage_bytes(h->precision);
+        std::vector<unsigned char> raw(9 * plane * sb);
+        HIPCHK(h, hipMemcpyAsync(raw.data(), R.f[h->pf], raw.size(), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int i = 0; i < 9; ++i)
+            for (int y = 0; y < R.ny; ++y)
+                for (int x = 0; x < R.nx; ++x) {
+                    double v = ld_storage(raw.data(), h->precision, (size_t)i * plane + (size_t)y * R.pitch + x);
+                    if (h->precision >= 2) v += (double)(float)(kW[i] * R.shift);
+                    fstar[((size_t)i * R.ny + y) * R.nx + x] = v;
+                }
+    }
+    if (hist) {
+        const size_t cb = compute_bytes(h->precision);
+        std::vector<unsigned char> raw(3 * (size_t)R.ny * cb);
+        HIPCHK(h, hipMemcpyAsync(raw.data(), R.hist[h->ph], raw.size(), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (size_t k = 0; k < 3 * (size_t)R.ny; ++k) hist[k] = ld_compute(raw.data(), h->precision, k);
+    }
+    if (T) {
+        std::vector<double> buf;
+        if ((rc = download_plane(h, R, R.T[h->pt], buf))) return rc;
+        std::copy(buf.begin(), buf.end(), T);
+    }
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *hist, const double *T, int64_t step)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!fstar || !hist || !T) return fail(h, LBM_EINVAL, "fstar, hist and T are required");
+    const RunDev &R = h->runs[run];
+    const size_t plane = (size_t)R.ny * R.pitch;
+    const size_t sb = storage_bytes(h->precision), cb = compute_bytes(h->precision);
+    std::vector<unsigned char> raw(9 * plane * sb, 0);
+    for (int i = 0; i < 9; ++i)
+        for (int y = 0; y < R.ny; ++y)
+            for (int x = 0; x < R.nx; ++x) {
+                double v = fstar[((size_t)i * R.ny + y) * R.nx + x];
+                if (h->precision >= 2) v -= (double)(float)(kW[i] * R.shift);
+                st_storage(raw.data(), h->precision, (size_t)i * plane + (size_t)y * R.pitch + x, v);
+            }
+    HIPCHK(h, hipMemcpyAsync(R.f[h->pf], raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream));
+    std::vector<unsigned char> hraw(3 * (size_t)R.ny * cb);
+    for (size_t k = 0; k < 3 * (size_t)R.ny; ++k) st_compute(hraw.data(), h->precision, k, hist[k]);
+    HIPCHK(h, hipMemcpyAsync(R.hist[h->ph], hraw.data(), hraw.size(), hipMemcpyHostToDevice, h->stream));
+    std::vector<double> Tw((size_t)R.nx * R.ny);
+    for (int y = 0; y < R.ny; ++y)
+        for (int x = 0; x < R.nx; ++x) {
+            const size_t k = (size_t)y * R.nx + x;
+            Tw[k] = solid_host(R, x, y) ? R.T_w : T[k];
+        }
+    if ((rc = upload_plane(h, R, R.T[h->pt], Tw.data(), 0))) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->step = step;
+    return LBM_OK;
+}
+
+int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, double *nu_time_avg)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if ((rc = moments_pass(h, run))) return rc;
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->runs[run], h->pt, 0, h->stream));
+    double acc[8];
+    HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (q_mean) *q_mean = acc[1];
+    if (nu) *nu = acc[2];
+    if (nu_time_avg) *nu_time_avg = acc[4] > 0 ? acc[3] / acc[4] : 0.0;
+    return LBM_OK;
+}
+
+int lbm_total_mass(lbm_handle *h, int run, double *mass)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if ((rc = moments_pass(h, run))) return rc;
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->runs[run], h->pt, 0, h->stream));
+    double acc[8];
+    HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (mass) *mass = acc[0];
+    return LBM_OK;
+}
+
+int lbm_derived(lbm_handle *h, int run, double *out8)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!out8) return fail(h, LBM_EINVAL, "out8 is NULL");
+    const RunDev &R = h->runs[run];
+    const double v[8] = {R.Tc, R.T_sat, R.T_w, R.rho_l, R.rho_v, R.rho_w, R.rho_gref, R.omega};
+    std::memcpy(out8, v, sizeof(v));
+    return LBM_OK;
+}
+
+int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
+{
+    if (!h) return LBM_EINVAL;
+    if (n_launches < 0) return fail(h, LBM_EINVAL, "negative launch count");
+    if (kernel == LBM_KERNEL_STREAM_COLLIDE) {
+        for (int k = 0; k < n_launches; ++k)
+            HIPCHK(h, lbm::launch_lbm(h->precision, true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
+                                      h->step, h->stream));
+        return LBM_OK;
+    }
+    if (kernel == LBM_KERNEL_THERMAL) {
+        if (h->rk == 0) return fail(h, LBM_EINVAL, "runs have no temperature update");
+        for (int k = 0; k < n_launches; ++k)
+            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
+                                          h->stream));
+        return LBM_OK;
+    }
+    return fail(h, LBM_EINVAL, "unknown kernel %d", kernel);
+}
+
+int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
+
+const char *lbm_last_error(const lbm_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void lbm_destroy(lbm_handle *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Internal interface between the C-ABI host code (lbm_api.cpp) and the gfx950 kernels
+// (lbm_kernels.hip).  Not installed; the public interface is include/lbm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kMaxProbes = 4096;
+constexpr int kDiagBlocks = 256;
+
+// Per-run description read by every kernel.  Physical constants are kept in FP64 and converted
+// to the compute type inside the kernels.
+struct RunDev {
+    int nx, ny, pitch;        // pitch: row stride in elements (multiple of 64)
+    int bc_x;                 // 0 periodic, 1 inlet/outlet
+    int cyl_x, cyl_y, cyl_r;  // cyl_r <= 0: no cylinder
+    int rk;                   // 0, 2, 4
+    int upwind_kind;
+    int warmup;
+    int np;                   // wall probes
+    int pad0;
+    double omega, sigma, G, gx, gy, rho_gref, rho_w, rho_l, rho_v;
+    double T_sat, T_w, Tc, kappa, eos_a, eos_b, eos_R;
+    double u_in, alpha, cv, shift;
+    void *f[2];               // populations, storage type, [9][ny][pitch]
+    void *T[2];               // temperature, compute type, [ny][pitch]
+    void *rho, *ux, *uy;      // macroscopic fields of the last streamed state, compute type
+    void *hist[2];            // outlet history, compute type, [3][ny]
+    const double *probes;     // [np][2] probe coordinates
+    double *partials;         // [kDiagBlocks] partial mass sums
+    double *acc;              // [8]: mass, q_mean, nu, nu_sum, nu_count, nonfinite
+};
+
+// One work item: run index and tile coordinates.
+struct Tile {
+    int run, tx, ty, pad;
+};
+
+// Launch geometry of a precision: tile shapes of the two stencil kernels.
+struct TileShape {
+    int lbm_tx, lbm_ty, th_tx, th_ty;
+};
+
+TileShape tile_shape(int precision, int rk);
+
+// Launchers (each enqueues on `stream`; returns a hipError_t).
+hipError_t launch_init(int precision, const RunDev *runs_dev, int run, const RunDev &host_run,
+                       hipStream_t stream);
+hipError_t launch_lbm(int precision, bool write_f, const RunDev *runs_dev, const Tile *tiles,
+                      int n_tiles, int parity_f, int parity_t, int parity_h, long long step,
+                      hipStream_t stream);
+hipError_t launch_thermal(int precision, int rk, const RunDev *runs_dev, const Tile *tiles,
+                          int n_tiles, int parity_t, long long step, hipStream_t stream);
+hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, const RunDev &host_run,
+                       int parity_t, int accumulate, hipStream_t stream);
+
+}  // namespace lbm

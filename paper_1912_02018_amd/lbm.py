@@ -1,0 +1,207 @@
+"""Thin ctypes binding of liblbm (include/lbm.h); argument marshalling only.
+
+Every step of the method runs in the HIP kernels of liblbm.so.  PyTorch provides the device
+workspace (a uint8 tensor) and the stream.  If the library is missing this module raises: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+import numpy as np
+
+from .config import LBMConfig
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+_CONFIG_FIELDS = [
+    ("nx", C.c_int32), ("ny", C.c_int32), ("bc_x", C.c_int32), ("rk_stages", C.c_int32),
+    ("warmup_steps", C.c_int32), ("cyl_x", C.c_int32), ("cyl_y", C.c_int32), ("cyl_r", C.c_int32),
+    ("upwind_kind", C.c_int32), ("diag_every", C.c_int32),
+    ("nu", C.c_double), ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double),
+    ("acentric", C.c_double), ("Tr_sat", C.c_double), ("dTr_wall", C.c_double),
+    ("G", C.c_double), ("sigma", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+    ("rho_gref", C.c_double), ("rho_l", C.c_double), ("rho_v", C.c_double),
+    ("rho_wall", C.c_double), ("u_in", C.c_double), ("alpha_T", C.c_double), ("cv", C.c_double),
+    ("precision", C.c_int32), ("check_every", C.c_int32), ("rho_ref_shift", C.c_double),
+]
+
+EXPORTED = [
+    "lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_fields", "lbm_set_fields",
+    "lbm_get_state", "lbm_set_state", "lbm_wall_heat_flux", "lbm_total_mass", "lbm_derived",
+    "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
+]
+KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
+
+
+class lbm_config(C.Structure):
+    _fields_ = _CONFIG_FIELDS
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbm.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python paper_1912_02018_amd/build.py")
+    import torch  # noqa: F401  (loads the HIP runtime first)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int, C.c_int64, C.POINTER(C.c_double)
+    cfgp = C.POINTER(lbm_config)
+    L.lbm_workspace_bytes.argtypes = [cfgp, i32]
+    L.lbm_workspace_bytes.restype = C.c_size_t
+    L.lbm_create.argtypes = [cfgp, i32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_step.argtypes = [vp, i32]
+    L.lbm_fields.argtypes = [vp, i32, dp, dp, dp, dp, C.POINTER(C.c_uint8)]
+    L.lbm_set_fields.argtypes = [vp, i32, dp, dp, dp, dp]
+    L.lbm_get_state.argtypes = [vp, i32, dp, dp, dp]
+    L.lbm_set_state.argtypes = [vp, i32, dp, dp, dp, i64]
+    L.lbm_wall_heat_flux.argtypes = [vp, i32, dp, dp, dp]
+    L.lbm_total_mass.argtypes = [vp, i32, dp]
+    L.lbm_derived.argtypes = [vp, i32, dp]
+    L.lbm_time_kernel.argtypes = [vp, i32, i32]
+    L.lbm_step_count.argtypes = [vp]
+    L.lbm_step_count.restype = i64
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_destroy.restype = None
+    _lib = L
+    return L
+
+
+def to_c_config(cfg: LBMConfig) -> lbm_config:
+    c = lbm_config()
+    for name, _ in _CONFIG_FIELDS:
+        setattr(c, name, getattr(cfg, name))
+    return c
+
+
+def _dp(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def workspace_bytes(cfgs: Sequence[LBMConfig]) -> int:
+    L = load_library()
+    arr = (lbm_config * len(cfgs))(*[to_c_config(c) for c in cfgs])
+    n = L.lbm_workspace_bytes(arr, len(cfgs))
+    if n == 0:
+        raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
+    return n
+
+
+class Simulation:
+    """One handle stepping one or more runs on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, cfgs, device: str = "cuda", stream=None):
+        import torch
+        if isinstance(cfgs, LBMConfig):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        L = load_library()
+        self._L = L
+        n = len(self.cfgs)
+        arr = (lbm_config * n)(*[to_c_config(c) for c in self.cfgs])
+        nbytes = L.lbm_workspace_bytes(arr, n)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        rc = L.lbm_create(arr, n, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != LBM_OK:
+            raise LBMError(rc, L.lbm_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc: int):
+        if rc != LBM_OK:
+            raise LBMError(rc, self._L.lbm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def step_count(self) -> int:
+        return int(self._L.lbm_step_count(self.h))
+
+    def step(self, n: int = 1):
+        self._check(self._L.lbm_step(self.h, int(n)))
+
+    def _shape(self, run):
+        c = self.cfgs[run]
+        return (c.ny, c.nx)
+
+    def time_kernel(self, kernel: int, n: int):
+        """Enqueue n launches of one kernel of the step without advancing the state."""
+        self._check(self._L.lbm_time_kernel(self.h, int(kernel), int(n)))
+
+    def set_fields(self, rho, ux, uy, T=None, run: int = 0):
+        shp = self._shape(run)
+        f = lambda a: None if a is None else np.ascontiguousarray(np.broadcast_to(a, shp), dtype=np.float64)
+        rho, ux, uy, T = f(rho), f(ux), f(uy), f(T)
+        self._check(self._L.lbm_set_fields(self.h, run, _dp(rho), _dp(ux), _dp(uy), _dp(T)))
+
+    def fields(self, run: int = 0):
+        shp = self._shape(run)
+        rho, ux, uy, T = (np.zeros(shp) for _ in range(4))
+        mask = np.zeros(shp, dtype=np.uint8)
+        self._check(self._L.lbm_fields(self.h, run, _dp(rho), _dp(ux), _dp(uy), _dp(T),
+                                       mask.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return {"rho": rho, "ux": ux, "uy": uy, "T": T, "mask": mask}
+
+    def get_state(self, run: int = 0):
+        ny, nx = self._shape(run)
+        fstar, hist, T = np.zeros((9, ny, nx)), np.zeros((3, ny)), np.zeros((ny, nx))
+        self._check(self._L.lbm_get_state(self.h, run, _dp(fstar), _dp(hist), _dp(T)))
+        return fstar, hist, T, self.step_count
+
+    def set_state(self, fstar, hist, T, step: int, run: int = 0):
+        ny, nx = self._shape(run)
+        fstar = np.ascontiguousarray(fstar, dtype=np.float64).reshape(9, ny, nx)
+        hist = np.ascontiguousarray(hist, dtype=np.float64).reshape(3, ny)
+        T = np.ascontiguousarray(T, dtype=np.float64).reshape(ny, nx)
+        self._check(self._L.lbm_set_state(self.h, run, _dp(fstar), _dp(hist), _dp(T), int(step)))
+
+    def wall_heat_flux(self, run: int = 0):
+        q, nu, nua = C.c_double(), C.c_double(), C.c_double()
+        self._check(self._L.lbm_wall_heat_flux(self.h, run, C.byref(q), C.byref(nu), C.byref(nua)))
+        return q.value, nu.value, nua.value
+
+    def total_mass(self, run: int = 0) -> float:
+        m = C.c_double()
+        self._check(self._L.lbm_total_mass(self.h, run, C.byref(m)))
+        return m.value
+
+    def derived(self, run: int = 0):
+        out = np.zeros(8)
+        self._check(self._L.lbm_derived(self.h, run, _dp(out)))
+        keys = ["Tc", "T_sat", "T_w", "rho_l", "rho_v", "rho_w", "rho_gref", "omega"]
+        return dict(zip(keys, out.tolist()))

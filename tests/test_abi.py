@@ -1,0 +1,69 @@
+"""The C-ABI library loads on any host and exports every entry point include/lbm.h declares;
+host-side validation and workspace sizing (no device calls)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1912_02018_amd import lbm
+from paper_1912_02018_amd.config import LBMConfig, config1, config2, config5, sweep_configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", hdr))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load_library()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.split()[-1].startswith("lbm_")}
+    assert declared_symbols() == exported
+    assert set(lbm.EXPORTED) == declared_symbols()
+
+
+def test_config_struct_matches_header_field_order():
+    hdr = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    body = hdr[hdr.index("typedef struct {"):hdr.index("} lbm_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.replace("typedef struct {", "").strip()
+        if not decl:
+            continue
+        parts = decl.split(None, 1)
+        names += [n.strip() for n in parts[1].split(",")]
+    assert names == [n for n, _ in lbm._CONFIG_FIELDS]
+
+
+def test_workspace_sizes():
+    b1 = lbm.workspace_bytes([config1()])
+    b2 = lbm.workspace_bytes([config2()])
+    # FP64 state: 2 x 9 population planes + 5 scalar planes of 128x64 nodes
+    assert b1 >= (18 + 5) * 8 * 128 * 64
+    # FP32 state of 1024x512
+    assert b2 >= (18 + 5) * 4 * 1024 * 512
+    assert b2 < 1.2 * (18 + 5) * 4 * 1024 * 512 + (1 << 20)
+    runs = sweep_configs(8)
+    assert lbm.workspace_bytes(runs) >= sum(lbm.workspace_bytes([r]) for r in runs) - 8 * 4096
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2), dict(ny=3), dict(bc_x=2), dict(precision=7), dict(rk_stages=3), dict(nu=0.0),
+    dict(G=0.0), dict(cyl_r=30, cyl_x=20), dict(warmup_steps=-1),
+])
+def test_invalid_configs_rejected(bad):
+    cfg = LBMConfig(nx=64, ny=32, cyl_x=20, cyl_y=16, cyl_r=5, alpha_T=0.01).replace(**bad)
+    with pytest.raises(lbm.LBMError):
+        lbm.workspace_bytes([cfg])
+
+
+def test_mixed_precision_batch_rejected():
+    with pytest.raises(lbm.LBMError):
+        lbm.workspace_bytes([config5(), config5().replace(precision=0)])

@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64: max-norm relative error ||a_gpu - a_ref||_inf / ||a_ref||_inf <= 1e-12 per 1000 steps for
+rho, T and the post-collision populations, and for the velocity vector relative to
+max(||u||_inf, u_ref).  The two sides differ only by rounding order (closed-form reconstruction
+versus LU solve, tree versus serial sums, FMA contraction).  FP32 runs are compared with the
+oracle stepped one step from the same state, within bounds set by FP32 rounding of one step
+(unit roundoff 6e-8 times a dependent chain of ~30 operations: 2e-6; 2e-5 for the velocity, a
+difference of populations), and after 1000 steps with the accumulated bound stated in the test.
+Sizes span several tiles and ragged tails.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_02018_amd import inputs
+from paper_1912_02018_amd.config import (LBMConfig, FP64, FP32, BC_PERIODIC, BC_INLET_OUTLET,
+                                         config1, config2, cylinder_config)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+COEX = json.load(open(os.path.join(GOLDEN, "maxwell_coexistence.json")))["coexistence"]
+TOL64 = 1e-12
+
+
+def coex(tr=0.86):
+    c = COEX[f"{tr:.2f}"]
+    return c["rho_l"], c["rho_v"]
+
+
+@pytest.fixture(scope="module")
+def lbm_mod():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1912_02018_amd import lbm
+    return lbm
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def compare(sim, ref, label, tol=TOL64, tol_u=None, u_ref=0.01, run=0):
+    """Relative max-norm differences of rho, T and the populations f*; velocity as a vector,
+    relative to max(||u||_inf, u_ref) so that a flow decaying towards rest is not judged against
+    its own vanishing scale (u_ref = inlet velocity for channels, 0.01 otherwise)."""
+    g, o = sim.fields(run), ref.fields()
+    assert np.array_equal(g["mask"], o["mask"])
+    fluid = o["mask"] == 0
+    errs = {k: rel(g[k][fluid], o[k][fluid]) for k in ("rho", "T")}
+    du = np.hypot(g["ux"] - o["ux"], g["uy"] - o["uy"])[fluid].max()
+    umax = np.hypot(o["ux"], o["uy"])[fluid].max()
+    errs["u"] = float(du / max(umax, u_ref))
+    fg, _, _, _ = sim.get_state(run)
+    fo, _, _, _ = ref.get_state()
+    errs["f*"] = max(rel(fg[i][fluid], fo[i][fluid]) for i in range(9))
+    print(f"[parity] {label}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+          + f" (|u|max {umax:.3e})", flush=True)
+    for k, v in errs.items():
+        t = tol_u if (tol_u is not None and k == "u") else tol
+        assert v <= t, (label, k, v)
+    return errs
+
+
+def run_pair(lbm, cfg, steps, fields=None):
+    sim = lbm.Simulation(cfg)
+    ref = oracle.Sim(cfg)
+    if fields is not None:
+        sim.set_fields(*fields)
+        ref.set_fields(*fields)
+    sim.step(steps)
+    ref.step(steps)
+    return sim, ref
+
+
+@pytest.mark.parametrize("steps", [1000, 2000])
+def test_flat_interface_fp64(lbm_mod, steps):
+    rl, rv = coex()
+    cfg = config1().replace(rho_l=rl, rho_v=rv)
+    rho = inputs.slab(128, 64, 32, 96, rl, rv, 1e-3, 1912)
+    sim, ref = run_pair(lbm_mod, cfg, steps, (rho, 0.0, 0.0))
+    # rounding-order differences accumulate about linearly: 1e-12 per 1000 steps
+    compare(sim, ref, f"flat interface 128x64 {steps} steps", tol=TOL64 * steps / 1000)
+    m_g, m_o = sim.total_mass(), ref.total_mass()
+    assert abs(m_g / m_o - 1) < 1e-13
+    assert abs(m_g / (rho.sum()) - 1) < 1e-12
+
+
+def cylinder_case(nx=128, ny=64, r=8, cx=40, re=100.0, rk=4, precision=FP64, **kw):
+    rl, rv = coex()
+    cfg = cylinder_config(nx, ny, r, cx, re=re, u_in=0.02, dTr_wall=0.1, precision=precision,
+                          warmup=0, rk_stages=rk, diag_every=10)
+    return cfg.replace(rho_l=rl, rho_v=rv, **kw)
+
+
+def test_heated_cylinder_channel_fp64(lbm_mod):
+    cfg = cylinder_case()
+    sim, ref = run_pair(lbm_mod, cfg, 1000)
+    compare(sim, ref, "cylinder 128x64 R8 RK4 1000 steps", u_ref=cfg.u_in)
+    qg, nug, nuag = sim.wall_heat_flux()
+    qo, nuo, nuao = ref.wall_heat_flux()
+    print(f"[parity] heat flux gpu {qg:.10e} {nug:.10e} {nuag:.10e} oracle {qo:.10e} {nuo:.10e} {nuao:.10e}", flush=True)
+    assert abs(qg / qo - 1) < TOL64 and abs(nug / nuo - 1) < TOL64 and abs(nuag / nuao - 1) < TOL64
+    assert abs(sim.total_mass() / ref.total_mass() - 1) < TOL64
+
+
+def test_ragged_tiles_rk2_kawamura_kuwahara_fp64(lbm_mod):
+    cfg = cylinder_case(nx=100, ny=50, r=6, cx=30, rk=2, upwind_kind=1)
+    sim, ref = run_pair(lbm_mod, cfg, 300)
+    compare(sim, ref, "cylinder 100x50 R6 RK2 KK 300 steps", u_ref=cfg.u_in)
+
+
+def test_periodic_array_with_gravity_fp64(lbm_mod):
+    rl, rv = coex()
+    cfg = LBMConfig(nx=72, ny=40, bc_x=BC_PERIODIC, cyl_x=36, cyl_y=20, cyl_r=7, rk_stages=4,
+                    nu=0.05, alpha_T=0.03, dTr_wall=0.05, gx=1e-5, gy=-2e-6, rho_gref=0.0,
+                    rho_l=rl, rho_v=rv, precision=FP64)
+    sim, ref = run_pair(lbm_mod, cfg, 300)
+    compare(sim, ref, "periodic cylinder array 72x40 300 steps")
+
+
+def test_tiny_grid_random_fields_fp64(lbm_mod):
+    rl, rv = coex()
+    cfg = LBMConfig(nx=5, ny=4, bc_x=BC_PERIODIC, rk_stages=4, nu=0.1, alpha_T=0.05,
+                    rho_l=rl, rho_v=rv, precision=FP64)
+    rho, ux, uy = inputs.random_fields(5, 4, rl, 1e-3, 1e-3, seed=11)
+    T = np.full((4, 5), 0.86 * COEX_TC()) * (1 + inputs.uniform_noise(12, (4, 5), 1e-3))
+    sim, ref = run_pair(lbm_mod, cfg, 200, (rho, ux, uy, T))
+    compare(sim, ref, "tiny 5x4 random 200 steps")
+
+
+def COEX_TC():
+    return json.load(open(os.path.join(GOLDEN, "maxwell_coexistence.json")))["Tc"]
+
+
+def test_warmup_switch_fp64(lbm_mod):
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30).replace(warmup_steps=40)
+    sim, ref = run_pair(lbm_mod, cfg, 100)
+    compare(sim, ref, "warm-up 40 then 60 coupled steps", u_ref=cfg.u_in)
+
+
+def test_state_roundtrip_and_reproducibility(lbm_mod):
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30)
+    a = lbm_mod.Simulation(cfg)
+    a.step(50)
+    fs, hist, T, step = a.get_state()
+    b = lbm_mod.Simulation(cfg)
+    b.set_state(fs, hist, T, step)
+    a.step(50)
+    b.step(50)
+    sa, sb = a.get_state(), b.get_state()
+    assert all(np.array_equal(x, y) for x, y in zip(sa[:3], sb[:3]))
+
+
+def developed_state(lbm, cfg, steps):
+    sim = lbm.Simulation(cfg)
+    sim.step(steps)
+    return sim
+
+
+@pytest.mark.parametrize("precision,tol,tol_u", [(FP64, TOL64, TOL64), (FP32, 2e-6, 2e-5)])
+def test_full_size_one_step(lbm_mod, precision, tol, tol_u):
+    """1024x512 boiling channel (bench launch configuration): after 200 coupled steps on the GPU
+    the oracle takes the GPU state and both advance one step."""
+    rl, rv = coex()
+    cfg = config2(precision).replace(warmup_steps=0, rho_l=rl, rho_v=rv)
+    sim = developed_state(lbm_mod, cfg, 200)
+    fs, hist, T, step = sim.get_state()
+    ref = oracle.Sim(cfg.replace(precision=FP64))
+    ref.set_state(fs, hist, T, step)
+    sim.step(1)
+    ref.step(1)
+    compare(sim, ref, f"1024x512 one step from GPU state ({'fp64' if precision == FP64 else 'fp32'})",
+            tol=tol, tol_u=tol_u, u_ref=cfg.u_in)
+
+
+def test_fp32_error_after_1000_steps(lbm_mod):
+    """FP32 path against the FP64 oracle on the heated cylinder after 1000 steps."""
+    cfg64 = cylinder_case()
+    cfg32 = cfg64.replace(precision=FP32)
+    sim = lbm_mod.Simulation(cfg32)
+    ref = oracle.Sim(cfg64)
+    sim.step(1000)
+    ref.step(1000)
+    compare(sim, ref, "fp32 vs oracle cylinder 1000 steps", tol=1e-4, tol_u=1e-3, u_ref=cfg32.u_in)
