@@ -92,6 +92,13 @@ def main():
     ap.add_argument("--kernel-launches", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-physical-warmup", action="store_true",
+                    help="start coupled steps at once (short profiler runs; same per-step work)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variants")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep"],
+                    help="c2: 1024x512 boiling channel (default); c3: the same at Re 30000; sweep: 64 uneven runs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,48 +108,57 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+        return
     from paper_1912_02018_amd import lbm
-    from paper_1912_02018_amd.config import config2
+    from paper_1912_02018_amd.config import config2, config3, sweep_configs
 
     prec = PREC[args.precision]
-    cfg = config2(prec)
-    workload = f"boiling-cylinder-{cfg.nx}x{cfg.ny}-R{cfg.cyl_r}-Re300-rk{cfg.rk_stages}"
     torch.cuda.set_device(0)
-    sim = lbm.Simulation(cfg)
-    stream = sim.stream
-    sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
+    if args.workload == "sweep":
+        line = run_sweep(args, lbm, sweep_configs(64, 2018, prec), prec)
+    else:
+        cfg = config2(prec) if args.workload == "c2" else config3(prec)
+        re = 300 if args.workload == "c2" else 30000
+        if args.skip_physical_warmup:
+            cfg = cfg.replace(warmup_steps=0)
+        workload = f"boiling-cylinder-{cfg.nx}x{cfg.ny}-R{cfg.cyl_r}-Re{re}-rk{cfg.rk_stages}-{args.precision}"
+        line = run_single(args, lbm, cfg, prec, workload, re)
+    print(json.dumps(line), flush=True)
 
+
+def timed_steps(torch, sim, steps):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    nodes = cfg.nx * cfg.ny
-    mlups = nodes / (ms_step * 1e-3) / 1e6
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(steps)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
-    mass = sim.total_mass()
-    q, nu, nu_avg = sim.wall_heat_flux()
-    if not (mass == mass and nu == nu):
-        print("non-finite state after the timed steps", file=sys.stderr)
-        sys.exit(3)
 
-    # isolated launches of each kernel of the step, timed with HIP events on the same stream
+def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
+    """Average duration of isolated launches of each kernel of the step (HIP events on the
+    library's stream) and the roofline of the dominant one."""
     kt = {}
     for k in (0, 1):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         sim.time_kernel(k, 10)
-        e0.record(stream)
-        sim.time_kernel(k, args.kernel_launches)
-        e1.record(stream)
+        e0.record(sim.stream)
+        sim.time_kernel(k, launches)
+        e1.record(sim.stream)
         torch.cuda.synchronize()
-        kt[k] = e0.elapsed_time(e1) / args.kernel_launches  # ms per launch
+        kt[k] = e0.elapsed_time(e1) / launches  # ms per launch
     dom = max(kt, key=kt.get)
     name = KERNEL_NAMES[dom]
     if dom == 0:
@@ -160,10 +176,13 @@ def main():
     roof["kernel_ms"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in kt.items()}
     roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
                               for k, v in kt.items()}
+    return roof
 
-    line = {
+
+def base_line(args, prec, value, ms_step, workload_cfg):
+    return {
         "metric": "MLUPS (flow+thermal) & % HBM peak; batched vs single & FP16-store vs FP32 at error",
-        "value": round(mlups, 1),
+        "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -174,16 +193,74 @@ def main():
         "vs_baseline": None,
         "dtype": {0: "f64", 1: "f32", 2: "f16-store/f32", 3: "bf16-store/f32"}[prec],
         "data": "synthetic",
-        "config": {"workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r,
-                   "u_in": cfg.u_in, "Re": 300, "rk_stages": cfg.rk_stages,
-                   "warmup_steps_untimed": cfg.warmup_steps + args.warmup, "parallelism": "single-gpu"},
-        "roofline": roof,
-        "wall_s": round(wall, 3),
-        "diagnostics": {"mass": mass, "q_mean": q, "nu": nu},
+        "config": workload_cfg,
     }
+
+
+def run_single(args, lbm, cfg, prec, workload, re):
+    import torch
+    sim = lbm.Simulation(cfg)
+    sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
+    if not args.no_autotune:
+        sim.autotune(20)                # launch variants timed on the coupled state (untimed)
+    sim.step(args.warmup)
+    ms, wall = timed_steps(torch, sim, args.steps)
+    ms_step = ms / args.steps
+    nodes = cfg.nx * cfg.ny
+    mlups = nodes / (ms_step * 1e-3) / 1e6
+    mass = sim.total_mass()
+    q, nu, nu_avg = sim.wall_heat_flux()
+    if not (mass == mass and nu == nu):
+        print("non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(3)
+    line = base_line(args, prec, mlups, ms_step, {
+        "workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r, "u_in": cfg.u_in, "Re": re,
+        "rk_stages": cfg.rk_stages, "warmup_steps_untimed": cfg.warmup_steps + args.warmup,
+        "parallelism": "single-gpu",
+        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}})
+    line["roofline"] = kernel_roofline(torch, sim, cfg, prec, nodes, args.kernel_launches, workload)
+    line["wall_s"] = round(wall, 3)
+    line["diagnostics"] = {"mass": mass, "q_mean": q, "nu": nu}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_sweep(args, lbm, cfgs, prec):
+    """64 uneven boiling runs (superheat sweep) stepped together by one handle, against the same
+    runs stepped one after another through their own handles."""
+    import torch
+    nodes = sum(c.nx * c.ny for c in cfgs)
+    sim = lbm.Simulation(cfgs)
+    sim.step(max(c.warmup_steps for c in cfgs))
+    if not args.no_autotune:
+        sim.autotune(10)
+    sim.step(args.warmup)
+    ms, wall = timed_steps(torch, sim, args.steps)
+    ms_step = ms / args.steps
+    batched = nodes / (ms_step * 1e-3) / 1e6
+    # sequential: each run alone on its own handle (same configuration, warm-up already passed)
+    seq_steps = max(10, args.steps // 10)
+    seq_ms = 0.0
+    for c in cfgs:
+        one = lbm.Simulation(c.replace(warmup_steps=0))
+        one.step(20)
+        t_ms, _ = timed_steps(torch, one, seq_steps)
+        seq_ms += t_ms / seq_steps
+        one.close()
+        del one
+    sequential = nodes / (seq_ms * 1e-3) / 1e6
+    line = base_line(args, prec, batched, ms_step, {
+        "workload": f"boiling-sweep-{len(cfgs)}-runs", "runs": len(cfgs), "nodes": nodes,
+        "grids": "64*{4..16} x half, R 8..32, superheat 0.02..0.30 Tc, Re 30..3000 (seed 2018)",
+        "parallelism": "single-gpu",
+        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}})
+    line["sequential_mlups"] = round(sequential, 1)
+    line["batched_over_sequential"] = round(batched / sequential, 3)
+    line["roofline"] = kernel_roofline(torch, sim, cfgs[0], prec, nodes, max(10, args.kernel_launches // 10),
+                                       f"boiling-sweep-{len(cfgs)}-runs-{args.precision}")
+    line["wall_s"] = round(wall, 3)
+    return line
 
 
 if __name__ == "__main__":

@@ -137,6 +137,23 @@ int lbm_derived(lbm_handle *h, int run, double *out8);
 enum { LBM_KERNEL_STREAM_COLLIDE = 0, LBM_KERNEL_THERMAL = 1 };
 int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
 
+/* Launch variants of the stencil kernels (kernel 0: k_lbm, 1: k_thermal): each is a tile of
+ * tx x ty nodes per workgroup of `threads` threads.  lbm_set_variant rebuilds the tile tables
+ * (waits for the stream); lbm_autotune times every variant of both kernels on the handle's
+ * current state with HIP events (`launches` launches each) and keeps the fastest, writing the
+ * chosen indices to best[2] if not NULL. */
+int lbm_variant_count(int precision, int kernel);
+int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads);
+int lbm_set_variant(lbm_handle *h, int kernel, int variant);
+int lbm_get_variant(const lbm_handle *h, int kernel);
+int lbm_autotune(lbm_handle *h, int launches, int *best);
+
+/* Options.  LBM_OPT_GRAPHS (default 1): lbm_step captures one period of its launch pattern
+ * (2 steps, or the least common multiple with diag_every / check_every) into a HIP graph once
+ * every run is past its warm-up, and replays it; 0 launches every kernel directly. */
+enum { LBM_OPT_GRAPHS = 0 };
+int lbm_set_option(lbm_handle *h, int option, int value);
+
 /* Steps taken since creation / the last set_fields / set_state. */
 int64_t lbm_step_count(const lbm_handle *h);
 

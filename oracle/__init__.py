@@ -245,8 +245,11 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            lib().orc_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_destroy(h)
+            except Exception:
+                pass
             self.h = None
 
     def set_fields(self, rho, ux, uy, T=None):

@@ -18,6 +18,14 @@
 using lbm::RunDev;
 using lbm::Tile;
 
+// A captured window of steps, replayed while the launch pattern repeats.
+struct StepGraph {
+    int pf, pt, ph, length;
+    long long phase;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 struct lbm_handle {
     int n_runs = 0;
     int precision = 0;
@@ -27,10 +35,15 @@ struct lbm_handle {
     std::vector<RunDev> runs;         // host copies of the device descriptors
     RunDev *runs_dev = nullptr;
     Tile *tiles_lbm = nullptr, *tiles_th = nullptr;
+    int cap_lbm = 0, cap_th = 0;      // tile-table capacities (largest over the variants)
     std::vector<int> lbm_off, lbm_cnt, th_off, th_cnt;
     int n_lbm = 0, n_th = 0;
+    int var[2] = {0, 0};              // launch variant of k_lbm, k_thermal
     int pf = 0, pt = 0, ph = 0;
     long long step = 0;
+    bool use_graphs = true;
+    std::vector<StepGraph> graphs;
+    hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     std::string err;
 };
 
@@ -141,7 +154,8 @@ int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
     for (int r = 0; r < n; ++r) {
         const lbm_config &k = c[r];
         if (k.nx < 4 || k.ny < 4) return fail(h, LBM_EINVAL, "run %d: grid must be at least 4x4", r);
-        if ((long long)k.nx * k.ny > (1LL << 31)) return fail(h, LBM_EINVAL, "run %d: grid too large", r);
+        if (9.0 * k.ny * pitch_of(k.nx) * storage_bytes(k.precision) >= 4294967296.0)
+            return fail(h, LBM_EINVAL, "run %d: grid too large (9 population planes must stay below 4 GiB)", r);
         if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET) return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
         if (k.precision < 0 || k.precision > 3) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
         if (k.precision != c[0].precision) return fail(h, LBM_EINVAL, "all runs must share one precision");
@@ -183,15 +197,23 @@ size_t run_bytes(const lbm_config &k)
     return b;
 }
 
+int tile_count(const lbm_config *c, int n, lbm::Variant v)
+{
+    int t = 0;
+    for (int r = 0; r < n; ++r) t += ((c[r].nx + v.tx - 1) / v.tx) * ((c[r].ny + v.ty - 1) / v.ty);
+    return t;
+}
+
 Layout layout(const lbm_config *c, int n)
 {
     Layout L;
-    const lbm::TileShape ts = lbm::tile_shape(c[0].precision, c[0].rk_stages);
     L.n_lbm = L.n_th = 0;
-    for (int r = 0; r < n; ++r) {
-        L.n_lbm += ((c[r].nx + ts.lbm_tx - 1) / ts.lbm_tx) * ((c[r].ny + ts.lbm_ty - 1) / ts.lbm_ty);
-        L.n_th += ((c[r].nx + ts.th_tx - 1) / ts.th_tx) * ((c[r].ny + ts.th_ty - 1) / ts.th_ty);
-    }
+    for (int k = 0; k < 2; ++k)
+        for (int v = 0; v < lbm::variant_count(c[0].precision, k); ++v) {
+            const int t = tile_count(c, n, lbm::variant_shape(c[0].precision, k, v));
+            if (k == 0) L.n_lbm = std::max(L.n_lbm, t);
+            else L.n_th = std::max(L.n_th, t);
+        }
     size_t off = 0;
     L.runs_off = off; off += align256(sizeof(RunDev) * n);
     L.tiles_lbm_off = off; off += align256(sizeof(Tile) * L.n_lbm);
@@ -241,6 +263,67 @@ bool solid_host(const RunDev &R, int x, int y)
     return dx * dx + dy * dy <= (long)R.cyl_r * R.cyl_r;
 }
 
+// Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD b mod 8), each XCD
+// with its own L2.  Reorder a run's row-major tile list so that XCD j receives a contiguous band of
+// tiles: the halo reads of neighbouring tiles then hit the same L2.
+void xcd_order(std::vector<Tile> &tiles, size_t off, size_t n)
+{
+    const size_t nx = 8;
+    if (n < 2 * nx || n % nx != 0) return;
+    std::vector<Tile> band(tiles.begin() + off, tiles.begin() + off + n);
+    const size_t chunk = n / nx;
+    for (size_t t = 0; t < n; ++t) {
+        const size_t j = t / chunk, k = t % chunk;
+        tiles[off + k * nx + j] = band[t];
+    }
+}
+
+int max_warmup(const lbm_handle *h)
+{
+    int m = 0;
+    for (const auto &k : h->cfgs) m = std::max(m, k.warmup_steps);
+    return m;
+}
+
+void drop_graphs(lbm_handle *h)
+{
+    for (auto &g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
+}
+
+// Build and upload the tile tables of the current launch variants (per-run contiguous ranges,
+// XCD-grouped order inside each range).
+int build_tiles(lbm_handle *h)
+{
+    std::vector<Tile> tl[2];
+    for (int k = 0; k < 2; ++k) {
+        const lbm::Variant v = lbm::variant_shape(h->precision, k, h->var[k]);
+        std::vector<int> &off = k == 0 ? h->lbm_off : h->th_off;
+        std::vector<int> &cnt = k == 0 ? h->lbm_cnt : h->th_cnt;
+        off.clear();
+        cnt.clear();
+        for (int r = 0; r < h->n_runs; ++r) {
+            const RunDev &R = h->runs[r];
+            off.push_back((int)tl[k].size());
+            for (int ty = 0; ty < (R.ny + v.ty - 1) / v.ty; ++ty)
+                for (int tx = 0; tx < (R.nx + v.tx - 1) / v.tx; ++tx) tl[k].push_back(Tile{r, tx, ty, 0});
+            cnt.push_back((int)tl[k].size() - off.back());
+            xcd_order(tl[k], off.back(), cnt.back());
+        }
+    }
+    if ((int)tl[0].size() > h->cap_lbm || (int)tl[1].size() > h->cap_th) return fail(h, LBM_EINVAL, "tile table overflow");
+    h->n_lbm = (int)tl[0].size();
+    h->n_th = (int)tl[1].size();
+    HIPCHK(h, hipMemcpyAsync(h->tiles_lbm, tl[0].data(), sizeof(Tile) * tl[0].size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->tiles_th, tl[1].data(), sizeof(Tile) * tl[1].size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    return LBM_OK;
+}
+
 int check_run(lbm_handle *h, int run)
 {
     if (!h) return LBM_EINVAL;
@@ -276,8 +359,8 @@ int download_plane(lbm_handle *h, const RunDev &R, const void *src, std::vector<
 // macroscopic pass of one run without collision (writes rho, ux, uy of the current state)
 int moments_pass(lbm_handle *h, int run)
 {
-    HIPCHK(h, lbm::launch_lbm(h->precision, false, h->runs_dev, h->tiles_lbm + h->lbm_off[run], h->lbm_cnt[run],
-                              h->pf, h->pt, h->ph, h->step, h->stream));
+    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], false, h->runs_dev, h->tiles_lbm + h->lbm_off[run],
+                              h->lbm_cnt[run], h->pf, h->pt, h->ph, h->step, h->stream));
     return LBM_OK;
 }
 
@@ -314,8 +397,8 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
     h->runs_dev = (RunDev *)(ws + L.runs_off);
     h->tiles_lbm = (Tile *)(ws + L.tiles_lbm_off);
     h->tiles_th = (Tile *)(ws + L.tiles_th_off);
-    const lbm::TileShape ts = lbm::tile_shape(prec, rk);
-    std::vector<Tile> tl, tt;
+    h->cap_lbm = L.n_lbm;
+    h->cap_th = L.n_th;
     std::vector<std::vector<double>> probes(n_runs);
 
     for (int r = 0; r < n_runs; ++r) {
@@ -368,26 +451,13 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
             probes[r][2 * q] = R.cyl_x + rr * std::cos(th);
             probes[r][2 * q + 1] = R.cyl_y + rr * std::sin(th);
         }
-        // tiles
-        h->lbm_off.push_back((int)tl.size());
-        for (int ty = 0; ty < (R.ny + ts.lbm_ty - 1) / ts.lbm_ty; ++ty)
-            for (int tx = 0; tx < (R.nx + ts.lbm_tx - 1) / ts.lbm_tx; ++tx) tl.push_back(Tile{r, tx, ty, 0});
-        h->lbm_cnt.push_back((int)tl.size() - h->lbm_off.back());
-        h->th_off.push_back((int)tt.size());
-        for (int ty = 0; ty < (R.ny + ts.th_ty - 1) / ts.th_ty; ++ty)
-            for (int tx = 0; tx < (R.nx + ts.th_tx - 1) / ts.th_tx; ++tx) tt.push_back(Tile{r, tx, ty, 0});
-        h->th_cnt.push_back((int)tt.size() - h->th_off.back());
     }
-    h->n_lbm = (int)tl.size();
-    h->n_th = (int)tt.size();
 
     auto upload = [&](void *dst, const void *src, size_t bytes) -> int {
         HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
         return LBM_OK;
     };
-    if ((rc = upload(h->runs_dev, h->runs.data(), sizeof(RunDev) * n_runs)) ||
-        (rc = upload(h->tiles_lbm, tl.data(), sizeof(Tile) * tl.size())) ||
-        (rc = upload(h->tiles_th, tt.data(), sizeof(Tile) * tt.size()))) {
+    if ((rc = upload(h->runs_dev, h->runs.data(), sizeof(RunDev) * n_runs)) || (rc = build_tiles(h))) {
         g_create_error = h->err;
         delete h;
         return rc;
@@ -440,10 +510,55 @@ int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, 
         (rc = upload_plane(h, R, R.uy, uy, 0)) || (rc = upload_plane(h, R, R.T[0], T, R.T_sat)))
         return rc;
     HIPCHK(h, hipMemsetAsync(R.acc, 0, sizeof(double) * 8, h->stream));
-    HIPCHK(h, lbm::launch_init(h->precision, h->runs_dev, run, R, h->stream));
+    HIPCHK(h, lbm::launch_init(h->precision, h->runs_dev, run, (long long)R.nx * R.ny, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->step = 0;
     return LBM_OK;
+}
+
+// Enqueue the launches of one step (no host synchronisation).
+static int enqueue_step(lbm_handle *h)
+{
+    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
+                              h->step, h->stream));
+    bool thermal = false;
+    for (int r = 0; r < h->n_runs; ++r) {
+        const lbm_config &k = h->cfgs[r];
+        const bool fon = h->step >= k.warmup_steps;
+        const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
+        const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
+        if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, h->stream));
+        thermal |= fon && k.rk_stages > 0;
+    }
+    if (thermal) {
+        HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
+                                      h->stream));
+        h->pt ^= 1;
+    }
+    h->pf ^= 1;
+    h->ph ^= 1;
+    h->step += 1;
+    return LBM_OK;
+}
+
+static long long lcm_ll(long long a, long long b)
+{
+    long long x = a, y = b;
+    while (y) { long long t = x % y; x = y; y = t; }
+    return a / x * b;
+}
+
+// Length of the repeating launch pattern once every run is past its warm-up: populations and
+// outlet history alternate buffers every step, the temperature every step, and the Nu
+// accumulation / checks recur with their own periods.
+static long long pattern_length(const lbm_handle *h)
+{
+    long long L = 2;
+    for (const auto &k : h->cfgs) {
+        if (k.diag_every > 0) L = lcm_ll(L, k.diag_every);
+        if (k.check_every > 0) L = lcm_ll(L, k.check_every);
+    }
+    return L;
 }
 
 int lbm_step(lbm_handle *h, int n_steps)
@@ -451,26 +566,62 @@ int lbm_step(lbm_handle *h, int n_steps)
     if (!h) return LBM_EINVAL;
     if (n_steps < 0) return fail(h, LBM_EINVAL, "negative step count");
     bool any_check = false;
-    for (int r = 0; r < h->n_runs; ++r) any_check |= h->cfgs[r].check_every > 0;
-    for (int s = 0; s < n_steps; ++s) {
-        HIPCHK(h, lbm::launch_lbm(h->precision, true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph, h->step,
-                                  h->stream));
-        bool thermal = false;
-        for (int r = 0; r < h->n_runs; ++r) {
-            const lbm_config &k = h->cfgs[r];
-            const bool fon = h->step >= k.warmup_steps;
-            const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
-            const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
-            if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->runs[r], h->pt, acc ? 1 : 0, h->stream));
-            thermal |= fon && k.rk_stages > 0;
+    int max_warm = 0;
+    for (int r = 0; r < h->n_runs; ++r) {
+        any_check |= h->cfgs[r].check_every > 0;
+        max_warm = std::max(max_warm, h->cfgs[r].warmup_steps);
+    }
+    const long long L = pattern_length(h);
+    long long remaining = n_steps;
+    while (remaining > 0) {
+        // replay a captured window when the pattern repeats (all runs past warm-up, window aligned)
+        const bool periodic = h->step >= max_warm;
+        if (h->use_graphs && periodic && L <= 4096 && remaining >= L && h->step % L == 0) {
+            StepGraph *g = nullptr;
+            for (auto &c : h->graphs)
+                if (c.pf == h->pf && c.pt == h->pt && c.ph == h->ph && c.length == (int)L) g = &c;
+            if (!g) {
+                StepGraph c{h->pf, h->pt, h->ph, (int)L, h->step, nullptr, nullptr};
+                const int pf = h->pf, pt = h->pt, ph = h->ph;
+                const long long st = h->step;
+                // record on a private stream (the caller's may be the legacy default stream, which
+                // cannot be captured); the graph is launched on the caller's stream
+                if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+                hipStream_t user = h->stream;
+                h->stream = h->cap_stream;
+                hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+                int rc = LBM_OK;
+                if (e == hipSuccess) {
+                    for (long long k = 0; k < L && rc == LBM_OK; ++k) rc = enqueue_step(h);
+                    e = hipStreamEndCapture(h->stream, &c.graph);
+                }
+                h->stream = user;
+                // the capture only recorded work: restore the counters it advanced
+                h->pf = pf; h->pt = pt; h->ph = ph; h->step = st;
+                if (rc != LBM_OK) return rc;
+                if (e != hipSuccess) return fail(h, LBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+                HIPCHK(h, hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+                h->graphs.push_back(c);
+                g = &h->graphs.back();
+            }
+            const int pt0 = h->pt;
+            long long reps = remaining / L;
+            for (long long k = 0; k < reps; ++k) HIPCHK(h, hipGraphLaunch(g->exec, h->stream));
+            // parities return to their values after an even-length window
+            h->pt = pt0;
+            h->step += reps * L;
+            remaining -= reps * L;
+            continue;
         }
-        if (thermal) {
-            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step, h->stream));
-            h->pt ^= 1;
+        // eager steps until the window is aligned (or without graphs)
+        long long eager = remaining;
+        if (h->use_graphs && periodic) eager = std::min(eager, L - h->step % L);
+        else if (h->use_graphs && !periodic) eager = std::min(eager, (long long)max_warm - h->step);
+        for (long long k = 0; k < eager; ++k) {
+            int rc = enqueue_step(h);
+            if (rc) return rc;
         }
-        h->pf ^= 1;
-        h->ph ^= 1;
-        h->step += 1;
+        remaining -= eager;
     }
     if (any_check) {
         for (int r = 0; r < h->n_runs; ++r) {
@@ -578,7 +729,7 @@ int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, doubl
     int rc = check_run(h, run);
     if (rc) return rc;
     if ((rc = moments_pass(h, run))) return rc;
-    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->runs[run], h->pt, 0, h->stream));
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
     double acc[8];
     HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -593,7 +744,7 @@ int lbm_total_mass(lbm_handle *h, int run, double *mass)
     int rc = check_run(h, run);
     if (rc) return rc;
     if ((rc = moments_pass(h, run))) return rc;
-    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->runs[run], h->pt, 0, h->stream));
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
     double acc[8];
     HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -618,18 +769,95 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
     if (n_launches < 0) return fail(h, LBM_EINVAL, "negative launch count");
     if (kernel == LBM_KERNEL_STREAM_COLLIDE) {
         for (int k = 0; k < n_launches; ++k)
-            HIPCHK(h, lbm::launch_lbm(h->precision, true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
-                                      h->step, h->stream));
+            HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt,
+                                      h->ph, h->step, h->stream));
         return LBM_OK;
     }
     if (kernel == LBM_KERNEL_THERMAL) {
         if (h->rk == 0) return fail(h, LBM_EINVAL, "runs have no temperature update");
         for (int k = 0; k < n_launches; ++k)
-            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
-                                          h->stream));
+            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->runs_dev, h->tiles_th, h->n_th, h->pt,
+                                          std::max<long long>(h->step, max_warmup(h)), h->stream));
         return LBM_OK;
     }
     return fail(h, LBM_EINVAL, "unknown kernel %d", kernel);
+}
+
+int lbm_variant_count(int precision, int kernel)
+{
+    if (precision < 0 || precision > 3 || kernel < 0 || kernel > 1) return 0;
+    return lbm::variant_count(precision, kernel);
+}
+
+int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads)
+{
+    const lbm::Variant v = lbm::variant_shape(precision, kernel, variant);
+    if (v.tx == 0) return LBM_EINVAL;
+    if (tx) *tx = v.tx;
+    if (ty) *ty = v.ty;
+    if (threads) *threads = v.nt;
+    return LBM_OK;
+}
+
+int lbm_set_variant(lbm_handle *h, int kernel, int variant)
+{
+    if (!h) return LBM_EINVAL;
+    if (kernel < 0 || kernel > 1 || variant < 0 || variant >= lbm::variant_count(h->precision, kernel))
+        return fail(h, LBM_EINVAL, "no variant %d of kernel %d", variant, kernel);
+    const int old = h->var[kernel];
+    h->var[kernel] = variant;
+    int rc = build_tiles(h);
+    if (rc) h->var[kernel] = old;
+    return rc;
+}
+
+int lbm_get_variant(const lbm_handle *h, int kernel)
+{
+    if (!h || kernel < 0 || kernel > 1) return -1;
+    return h->var[kernel];
+}
+
+int lbm_autotune(lbm_handle *h, int launches, int *best)
+{
+    if (!h) return LBM_EINVAL;
+    if (launches <= 0) launches = 20;
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && h->rk == 0) continue;
+        float best_ms = 1e30f;
+        int best_v = h->var[k];
+        for (int v = 0; v < lbm::variant_count(h->precision, k); ++v) {
+            int rc = lbm_set_variant(h, k, v);
+            if (rc) return rc;
+            if ((rc = lbm_time_kernel(h, k, 3))) return rc;
+            HIPCHK(h, hipEventRecord(e0, h->stream));
+            if ((rc = lbm_time_kernel(h, k, launches))) return rc;
+            HIPCHK(h, hipEventRecord(e1, h->stream));
+            HIPCHK(h, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best_v = v; }
+        }
+        int rc = lbm_set_variant(h, k, best_v);
+        if (rc) return rc;
+        if (best) best[k] = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return LBM_OK;
+}
+
+int lbm_set_option(lbm_handle *h, int option, int value)
+{
+    if (!h) return LBM_EINVAL;
+    if (option == LBM_OPT_GRAPHS) {
+        h->use_graphs = value != 0;
+        drop_graphs(h);
+        return LBM_OK;
+    }
+    return fail(h, LBM_EINVAL, "unknown option %d", option);
 }
 
 int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
@@ -640,6 +868,8 @@ void lbm_destroy(lbm_handle *h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
 

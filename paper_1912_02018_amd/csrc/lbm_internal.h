@@ -39,22 +39,22 @@ struct Tile {
     int run, tx, ty, pad;
 };
 
-// Launch geometry of a precision: tile shapes of the two stencil kernels.
-struct TileShape {
-    int lbm_tx, lbm_ty, th_tx, th_ty;
+// Launch variant of a stencil kernel: tile of tx x ty nodes per workgroup of nt threads.
+struct Variant {
+    int tx, ty, nt;
 };
 
-TileShape tile_shape(int precision, int rk);
+// kernel: 0 = stream+collide (k_lbm), 1 = temperature update (k_thermal)
+int variant_count(int precision, int kernel);
+Variant variant_shape(int precision, int kernel, int v);
 
 // Launchers (each enqueues on `stream`; returns a hipError_t).
-hipError_t launch_init(int precision, const RunDev *runs_dev, int run, const RunDev &host_run,
+hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream);
+hipError_t launch_lbm(int precision, int variant, bool write_f, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                      int parity_f, int parity_t, int parity_h, long long step, hipStream_t stream);
+hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                          int parity_t, long long step, hipStream_t stream);
+hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int parity_t, int accumulate,
                        hipStream_t stream);
-hipError_t launch_lbm(int precision, bool write_f, const RunDev *runs_dev, const Tile *tiles,
-                      int n_tiles, int parity_f, int parity_t, int parity_h, long long step,
-                      hipStream_t stream);
-hipError_t launch_thermal(int precision, int rk, const RunDev *runs_dev, const Tile *tiles,
-                          int n_tiles, int parity_t, long long step, hipStream_t stream);
-hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, const RunDev &host_run,
-                       int parity_t, int accumulate, hipStream_t stream);
 
 }  // namespace lbm

@@ -14,7 +14,8 @@
 //              carrying a halo of 2 nodes per stage so the stages never leave the CU.
 //   k_diag_*   FP64 mass and wall heat-flux reductions in a fixed order (bitwise reproducible).
 //   k_init     f* := f^eq(rho, u), outlet history, temperature from host-provided fields.
-// No MFMA: every kernel is a stencil or an elementwise map.
+// No MFMA: every kernel is a stencil or an elementwise map.  The 24-neighbour stencils are
+// evaluated on sums and differences of opposite neighbours, grouped by weight class.
 
 #include "lbm_internal.h"
 
@@ -26,6 +27,20 @@
 namespace lbm {
 namespace {
 
+// pointers into the workspace, in the global address space (global_load/store, not flat)
+template <typename T> using gp = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline gp<const T> gin(const void *p) { return (gp<const T>)p; }
+template <typename T> __device__ inline gp<T> gout(void *p) { return (gp<T>)p; }
+// element e of a workspace array, addressed with a 32-bit byte offset from a uniform base
+template <typename T> __device__ inline gp<T> at(void *base, unsigned e)
+{
+    return (gp<T>)((char *)base + e * (unsigned)sizeof(T));
+}
+template <typename T> __device__ inline T ld_at(const void *base, unsigned e)
+{
+    return *(gp<const T>)((const char *)base + e * (unsigned)sizeof(T));
+}
+
 // ------------------------------------------------------------------------------------------
 // Lattice (eq. velVec) and interaction-stencil weights (eq. interForce)
 // ------------------------------------------------------------------------------------------
@@ -33,50 +48,63 @@ __host__ __device__ constexpr int cx_of(int i) { return i == 1 || i == 5 || i ==
 __host__ __device__ constexpr int cy_of(int i) { return i == 3 || i == 5 || i == 8 ? 1 : (i == 4 || i == 6 || i == 7 ? -1 : 0); }
 __host__ __device__ constexpr int opp_of(int i) { return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1); }
 __host__ __device__ constexpr double lat_w(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
-__host__ __device__ constexpr double st_w(int e2)
-{
-    return e2 == 1 ? 4.0 / 21.0 : e2 == 2 ? 4.0 / 45.0 : e2 == 4 ? 1.0 / 60.0 : e2 == 5 ? 2.0 / 315.0 : e2 == 8 ? 1.0 / 5040.0 : 0.0;
-}
+constexpr double W1 = 4.0 / 21.0, W2 = 4.0 / 45.0, W4 = 1.0 / 60.0, W5 = 2.0 / 315.0, W8 = 1.0 / 5040.0;
+constexpr double WSUM = 4.0 * W1 + 4.0 * W2 + 4.0 * W4 + 8.0 * W5 + 4.0 * W8;
 
 // ------------------------------------------------------------------------------------------
-// Storage <-> compute conversion.  Reduced-precision storage holds f_i - w_i rho_ref.
+// Arithmetic of the compute type: IEEE division and square root in FP64; the native gfx950
+// reciprocal / square-root instructions (about 1 ulp) in FP32.
 // ------------------------------------------------------------------------------------------
+template <typename C> struct Ar;
+template <> struct Ar<double> {
+    __device__ static double rcp(double x) { return 1.0 / x; }
+    __device__ static double sqrt_(double x) { return sqrt(x); }
+};
+template <> struct Ar<float> {
+    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// ------------------------------------------------------------------------------------------
+// Storage type S, its raw bit type in memory, and the conversion to the compute type;
+// reduced-precision storage holds f_i - w_i rho_ref.
 template <typename S> struct Conv;
 template <> struct Conv<double> {
+    using raw = double;
     __device__ static double ld(double v, double) { return v; }
     __device__ static double st(double v, double) { return v; }
 };
 template <> struct Conv<float> {
+    using raw = float;
     __device__ static float ld(float v, float) { return v; }
     __device__ static float st(float v, float) { return v; }
 };
 template <> struct Conv<__half> {
-    __device__ static float ld(__half v, float s) { return __half2float(v) + s; }
-    __device__ static __half st(float v, float s) { return __float2half_rn(v - s); }
+    using raw = unsigned short;
+    __device__ static float ld(unsigned short v, float s) { return __half2float(__ushort_as_half(v)) + s; }
+    __device__ static unsigned short st(float v, float s) { return __half_as_ushort(__float2half_rn(v - s)); }
 };
 template <> struct Conv<__hip_bfloat16> {
-    __device__ static float ld(__hip_bfloat16 v, float s) { return __bfloat162float(v) + s; }
-    __device__ static __hip_bfloat16 st(float v, float s) { return __float2bfloat16(v - s); }
+    using raw = unsigned short;
+    __device__ static float ld(unsigned short v, float s) { return __uint_as_float((unsigned)v << 16) + s; }
+    __device__ static unsigned short st(float v, float s) { return __bfloat16_as_ushort(__float2bfloat16(v - s)); }
 };
+template <typename S> using RawT = typename Conv<S>::raw;
 
 template <typename S> using CT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
 
-__device__ inline int wrap_small(int a, int n)
+// periodic wrap of a coordinate (halos may span several periods of a tiny grid)
+__device__ inline int wrap(int a, int n)
 {
-    // a in [-n, 2n)
-    return a < 0 ? a + n : (a >= n ? a - n : a);
-}
-
-__device__ inline int wrap_any(int a, int n)
-{
-    int r = a % n;
-    return r < 0 ? r + n : r;
+    while (a < 0) a += n;
+    while (a >= n) a -= n;
+    return a;
 }
 
 __device__ inline bool solid_at(const RunDev &R, int x, int y)
 {
     if (R.cyl_r <= 0) return false;
-    int dx = x - R.cyl_x, dy = y - R.cyl_y;
+    const int dx = x - R.cyl_x, dy = y - R.cyl_y;
     return dx * dx + dy * dy <= R.cyl_r * R.cyl_r;
 }
 
@@ -84,12 +112,11 @@ __device__ inline bool solid_at(const RunDev &R, int x, int y)
 // rho/u of column 0, T = T_sat) or an outlet ghost column (x >= nx, copy of column nx-1).
 enum { NODE = 0, INLET_GHOST = 1, OUTLET_GHOST = 2 };
 
-// Map a lattice position to the domain node whose values it carries.
 __device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
 {
-    ry = wrap_any(gy, R.ny);
+    ry = wrap(gy, R.ny);
     if (R.bc_x == 0) {
-        rx = wrap_any(gx, R.nx);
+        rx = wrap(gx, R.nx);
         return NODE;
     }
     if (gx < 0) { rx = 0; return INLET_GHOST; }
@@ -102,121 +129,207 @@ __device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
 // Run constants in the compute type
 // ------------------------------------------------------------------------------------------
 template <typename C> struct Consts {
-    C omega, sigma, G, gx, gy, rho_gref, rho_w, T_sat, T_w, Tc, kappa, a, b, Rg, u_in, alpha, cv;
+    C omega, sigma, gx, gy, rho_gref, rho_w, T_sat, T_w, a, b, Rg, u_in;
+    C alpha, inv_cv, kappa, inv_sqrt_Tc, psi_scale, dphi_A, dphi_B;
     C shiftw[9];
     __device__ explicit Consts(const RunDev &R)
     {
-        omega = (C)R.omega; sigma = (C)R.sigma; G = (C)R.G; gx = (C)R.gx; gy = (C)R.gy;
+        omega = (C)R.omega; sigma = (C)R.sigma; gx = (C)R.gx; gy = (C)R.gy;
         rho_gref = (C)R.rho_gref; rho_w = (C)R.rho_w; T_sat = (C)R.T_sat; T_w = (C)R.T_w;
-        Tc = (C)R.Tc; kappa = (C)R.kappa; a = (C)R.eos_a; b = (C)R.eos_b; Rg = (C)R.eos_R;
-        u_in = (C)R.u_in; alpha = (C)R.alpha; cv = (C)R.cv;
+        a = (C)R.eos_a; b = (C)R.eos_b; Rg = (C)R.eos_R; u_in = (C)R.u_in;
+        alpha = (C)R.alpha; inv_cv = (C)(1.0 / R.cv); kappa = (C)R.kappa;
+        inv_sqrt_Tc = (C)(1.0 / sqrt(R.Tc));
+        psi_scale = (C)(2.0 / (R.G * (1.0 / 3.0)));
+        // phi'(T) = dphi_A / sqrt(T) + dphi_B
+        dphi_A = (C)(-R.kappa * (1.0 + R.kappa) / sqrt(R.Tc));
+        dphi_B = (C)(R.kappa * R.kappa / R.Tc);
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
 };
 
-// Peng-Robinson pressure (eq. eos) and the EOS-consistent pseudopotential (eq. potential).
-template <typename C> __device__ inline C pr_pressure(const Consts<C> &K, C rho, C T)
-{
-    C s = (C)1 + K.kappa * ((C)1 - sqrt(T / K.Tc));
-    C phi = s * s;
-    return rho * K.Rg * T / ((C)1 - K.b * rho) - K.a * phi * rho * rho / ((C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho);
-}
-
+// EOS-consistent pseudopotential (eq. potential) of the Peng-Robinson pressure (eq. eos)
 template <typename C> __device__ inline C pseudopotential(const Consts<C> &K, C rho, C T)
 {
-    const C cs2 = (C)(1.0 / 3.0);
-    C p = pr_pressure(K, rho, T);
-    return sqrt((C)2 * (p - rho * cs2) / (K.G * cs2));
+    const C s = (C)1 + K.kappa * ((C)1 - Ar<C>::sqrt_(T) * K.inv_sqrt_Tc);
+    const C phi = s * s;
+    const C d1 = (C)1 - K.b * rho;
+    const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
+    const C p = (rho * K.Rg * T * d2 - K.a * phi * rho * rho * d1) * Ar<C>::rcp(d1 * d2);
+    return Ar<C>::sqrt_((p - rho * (C)(1.0 / 3.0)) * K.psi_scale);
 }
 
 // ------------------------------------------------------------------------------------------
 // Streaming of one fluid node: f_i(x) = f*_i(x - c_i) with the boundary conditions
 // ------------------------------------------------------------------------------------------
+// Load population i at element offset (i * plane + y * pitch + x) of a population buffer.  The
+// byte offset is formed in 32 bits (9 planes stay below 4 GiB) so that the load takes the
+// scalar-base + 32-bit vector-offset form.
 template <typename S, typename C>
-__device__ inline C ldf(const S *__restrict__ f, size_t plane, int pitch, int i, int x, int y, const Consts<C> &K)
+__device__ inline C ldf(const char *base, unsigned plane, unsigned pitch, int i, int x, int y, const Consts<C> &K)
 {
-    return Conv<S>::ld(f[(size_t)i * plane + (size_t)y * pitch + x], K.shiftw[i]);
+    const unsigned off = ((unsigned)i * plane + (unsigned)y * pitch + (unsigned)x) * (unsigned)sizeof(RawT<S>);
+    return Conv<S>::ld(*(gp<const RawT<S>>)(base + off), K.shiftw[i]);
 }
 
 __device__ inline double link_q(const RunDev &R, int x, int y, int i)
 {
     // smaller root of |d - q c|^2 = R^2, d = node - centre (exact integers up to the sqrt)
-    double dx = x - R.cyl_x, dy = y - R.cyl_y, cx = cx_of(i), cy = cy_of(i);
-    double c2 = cx * cx + cy * cy, dc = dx * cx + dy * cy;
-    double Rr = R.cyl_r;
-    double disc = dc * dc - c2 * (dx * dx + dy * dy - Rr * Rr);
+    const double dx = x - R.cyl_x, dy = y - R.cyl_y, cx = cx_of(i), cy = cy_of(i);
+    const double c2 = cx * cx + cy * cy, dc = dx * cx + dy * cy;
+    const double Rr = R.cyl_r;
+    const double disc = dc * dc - c2 * (dx * dx + dy * dy - Rr * Rr);
     return (dc - sqrt(disc)) / c2;
 }
 
+// Plain pulls of a node away from the cylinder; at the inlet / outlet columns the sources outside
+// the domain are clamped in (their values are replaced by apply_x_bc).
 template <typename S, typename C>
-__device__ void stream_node(const RunDev &R, const Consts<C> &K, const S *__restrict__ fin,
-                            const C *__restrict__ hin, int x, int y, C f[9])
+__device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
     const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const size_t plane = (size_t)ny * P;
+    const unsigned plane = (unsigned)ny * P;
     const bool periodic = R.bc_x == 0;
     const int ym = y == 0 ? ny - 1 : y - 1;
     const int yp = y == ny - 1 ? 0 : y + 1;
-    const int xm = periodic ? (x == 0 ? nx - 1 : x - 1) : x - 1;
-    const int xp = periodic ? (x == nx - 1 ? 0 : x + 1) : x + 1;
-    const bool near = R.cyl_r > 0 && abs(x - R.cyl_x) <= R.cyl_r + 1 && abs(y - R.cyl_y) <= R.cyl_r + 1;
+    const int xm = x == 0 ? (periodic ? nx - 1 : 0) : x - 1;
+    const int xp = x == nx - 1 ? (periodic ? 0 : nx - 1) : x + 1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int xs = cx_of(i) > 0 ? xm : (cx_of(i) < 0 ? xp : x);
         const int ys = cy_of(i) > 0 ? ym : (cy_of(i) < 0 ? yp : y);
-        if (!periodic && (xs < 0 || xs >= nx)) { f[i] = (C)0; continue; }
-        if (near && solid_at(R, xs, ys)) {
-            // linear interpolated bounce-back on the curved wall
-            const int o = opp_of(i);
-            const double q = link_q(R, x, y, i);
-            const C fo = ldf<S, C>(fin, plane, P, o, x, y, K);
-            if (q < 0.5) {
-                int xn = x + cx_of(i), yn = wrap_small(y + cy_of(i), ny);
-                if (periodic) xn = wrap_small(xn, nx);
-                const bool fluid_n = xn >= 0 && xn < nx && !solid_at(R, xn, yn);
-                if (fluid_n) {
-                    const C q2 = (C)(2.0 * q);
-                    f[i] = q2 * fo + ((C)1 - q2) * ldf<S, C>(fin, plane, P, o, xn, yn, K);
-                } else {
-                    f[i] = fo;
-                }
-            } else {
+        f[i] = ldf<S, C>(fin, plane, P, i, xs, ys, K);
+    }
+}
+
+__device__ inline bool near_cylinder(const RunDev &R, int x, int y)
+{
+    return R.cyl_r > 0 && abs(x - R.cyl_x) <= R.cyl_r + 1 && abs(y - R.cyl_y) <= R.cyl_r + 1;
+}
+
+// Pulls of a node next to the cylinder: links whose source is solid use the linear interpolated
+// bounce-back on the curved wall.
+template <typename S, typename C>
+__device__ void pull_near(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
+{
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    const unsigned plane = (unsigned)ny * P;
+    const bool periodic = R.bc_x == 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int xs = x - cx_of(i), ys = wrap(y - cy_of(i), ny);
+        if (!solid_at(R, xs, ys)) {
+            f[i] = ldf<S, C>(fin, plane, P, i, xs, ys, K);
+            continue;
+        }
+        const int o = opp_of(i);
+        const double q = link_q(R, x, y, i);
+        const C fo = ldf<S, C>(fin, plane, P, o, x, y, K);
+        if (q < 0.5) {
+            int xn = x + cx_of(i);
+            const int yn = wrap(y + cy_of(i), ny);
+            if (periodic) xn = wrap(xn, nx);
+            const bool fluid_n = xn >= 0 && xn < nx && !solid_at(R, xn, yn);
+            if (fluid_n) {
                 const C q2 = (C)(2.0 * q);
-                f[i] = fo / q2 + (q2 - (C)1) / q2 * ldf<S, C>(fin, plane, P, i, x, y, K);
+                f[i] = q2 * fo + ((C)1 - q2) * ldf<S, C>(fin, plane, P, o, xn, yn, K);
+            } else {
+                f[i] = fo;
             }
         } else {
-            f[i] = ldf<S, C>(fin, plane, P, i, xs, ys, K);
+            const C q2 = (C)(2.0 * q);
+            f[i] = fo / q2 + (q2 - (C)1) / q2 * ldf<S, C>(fin, plane, P, i, x, y, K);
         }
     }
-    if (!periodic) {
-        if (x == nx - 1) {
-            // convective outflow: f^{n+1}(N) = (f^n(N) + U f^{n+1}(N-1)) / (1 + U), i in {2,6,8}
-            const C U = K.u_in;
-            const C p2 = ldf<S, C>(fin, plane, P, 2, nx - 1, y, K);
-            const C p6 = ldf<S, C>(fin, plane, P, 6, nx - 1, yp, K);
-            const C p8 = ldf<S, C>(fin, plane, P, 8, nx - 1, ym, K);
-            f[2] = (hin[0 * ny + y] + U * p2) / ((C)1 + U);
-            f[6] = (hin[1 * ny + y] + U * p6) / ((C)1 + U);
-            f[8] = (hin[2 * ny + y] + U * p8) / ((C)1 + U);
-        }
-        if (x == 0) {
-            // velocity inlet (u_in, 0): unknowns 1, 5, 7
-            const C u = K.u_in;
-            const C rin = (f[0] + f[3] + f[4] + (C)2 * (f[2] + f[6] + f[8])) / ((C)1 - u);
-            f[1] = f[2] + (C)(2.0 / 3.0) * rin * u;
-            f[5] = f[6] - (C)0.5 * (f[3] - f[4]) + rin * u / (C)6;
-            f[7] = f[8] + (C)0.5 * (f[3] - f[4]) + rin * u / (C)6;
-        }
+}
+
+// Velocity inlet at x = 0 and convective outlet at x = nx - 1.
+template <typename S, typename C>
+__device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, const char *fin, gp<const C> hin, int x,
+                                  int y, C f[9])
+{
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    const unsigned plane = (unsigned)ny * P;
+    if (x == nx - 1) {
+        // convective outflow: f^{n+1}(N) = (f^n(N) + U f^{n+1}(N-1)) / (1 + U), i in {2,6,8}
+        const int ym = y == 0 ? ny - 1 : y - 1;
+        const int yp = y == ny - 1 ? 0 : y + 1;
+        const C U = K.u_in;
+        const C inv = Ar<C>::rcp((C)1 + U);
+        const C p2 = ldf<S, C>(fin, plane, P, 2, nx - 1, y, K);
+        const C p6 = ldf<S, C>(fin, plane, P, 6, nx - 1, yp, K);
+        const C p8 = ldf<S, C>(fin, plane, P, 8, nx - 1, ym, K);
+        f[2] = (hin[0 * ny + y] + U * p2) * inv;
+        f[6] = (hin[1 * ny + y] + U * p6) * inv;
+        f[8] = (hin[2 * ny + y] + U * p8) * inv;
     }
+    if (x == 0) {
+        // velocity inlet (u_in, 0): unknowns 1, 5, 7
+        const C u = K.u_in;
+        const C rin = (f[0] + f[3] + f[4] + (C)2 * (f[2] + f[6] + f[8])) * Ar<C>::rcp((C)1 - u);
+        f[1] = f[2] + (C)(2.0 / 3.0) * rin * u;
+        f[5] = f[6] - (C)0.5 * (f[3] - f[4]) + rin * u * (C)(1.0 / 6.0);
+        f[7] = f[8] + (C)0.5 * (f[3] - f[4]) + rin * u * (C)(1.0 / 6.0);
+    }
+}
+
+template <typename C> struct F9 {
+    C v[9];
+};
+
+// Streaming of a node next to the cylinder or on an inlet / outlet column (rare; kept out of line
+// so the unrolled bulk path stays small).
+template <typename S, typename C>
+__device__ __attribute__((noinline)) F9<C> pull_special(const RunDev &R, const char *fin, const void *hin, int x, int y)
+{
+    const Consts<C> K(R);
+    F9<C> r;
+    if (near_cylinder(R, x, y)) pull_near<S, C>(R, K, fin, x, y, r.v);
+    else pull_bulk<S, C>(R, K, fin, x, y, r.v);
+    if (R.bc_x == 1 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, fin, gin<C>(hin), x, y, r.v);
+    return r;
+}
+
+// x and y components of sum_k w_k a(x + e_k) e_k from the differences of opposite neighbours
+template <typename C> struct PairD {
+    C d10, d01, d11, d1m, d20, d02, d21, d2m, d12, d1m2, d22, d2m2;
+    __device__ C gx() const
+    {
+        return (C)W1 * d10 + (C)W2 * (d11 + d1m) + (C)(2 * W4) * d20 + (C)W5 * ((C)2 * (d21 + d2m) + d12 + d1m2) +
+               (C)(2 * W8) * (d22 + d2m2);
+    }
+    __device__ C gy() const
+    {
+        return (C)W1 * d01 + (C)W2 * (d11 - d1m) + (C)(2 * W4) * d02 + (C)W5 * (d21 - d2m + (C)2 * (d12 - d1m2)) +
+               (C)(2 * W8) * (d22 - d2m2);
+    }
+};
+
+// differences of opposite neighbours of LDS position c in a row-major array of row stride RW
+template <int RW, typename C> __device__ inline PairD<C> pair_diffs(const C *s, int c)
+{
+    PairD<C> d;
+    d.d10 = s[c + 1] - s[c - 1];
+    d.d01 = s[c + RW] - s[c - RW];
+    d.d11 = s[c + RW + 1] - s[c - RW - 1];
+    d.d1m = s[c - RW + 1] - s[c + RW - 1];
+    d.d20 = s[c + 2] - s[c - 2];
+    d.d02 = s[c + 2 * RW] - s[c - 2 * RW];
+    d.d21 = s[c + RW + 2] - s[c - RW - 2];
+    d.d2m = s[c - RW + 2] - s[c + RW - 2];
+    d.d12 = s[c + 2 * RW + 1] - s[c - 2 * RW - 1];
+    d.d1m2 = s[c - 2 * RW + 1] - s[c + 2 * RW - 1];
+    d.d22 = s[c + 2 * RW + 2] - s[c - 2 * RW - 2];
+    d.d2m2 = s[c - 2 * RW + 2] - s[c + 2 * RW - 2];
+    return d;
 }
 
 // ------------------------------------------------------------------------------------------
 // k_lbm: streaming + moments + psi + force + central-moment collision
 // ------------------------------------------------------------------------------------------
-template <typename S, int TX, int TY, bool WRITE_F>
-__global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
-                                             int pf, int pt, int ph, long long step)
+template <typename S, int TX, int TY, int NT, bool WRITE_F>
+__global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pf,
+                                            int pt, int ph, long long step)
 {
     using C = CT<S>;
     constexpr int H = 2;
@@ -230,35 +343,65 @@ __global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, co
     const int x0 = t.tx * TX, y0 = t.ty * TY;
     const int nx = R.nx, ny = R.ny, P = R.pitch;
     const bool fon = step >= R.warmup;
-    const S *__restrict__ fin = (const S *)R.f[pf];
-    S *__restrict__ fout = (S *)R.f[pf ^ 1];
-    const C *__restrict__ Tc = (const C *)R.T[pt];
-    const C *__restrict__ hin = (const C *)R.hist[ph];
-    C *__restrict__ hout = (C *)R.hist[ph ^ 1];
+    const char *fin = (const char *)R.f[pf];
+    char *fout = (char *)R.f[pf ^ 1];
+    const gp<const C> Tc = gin<C>(R.T[pt]);
+    const gp<const C> hin = gin<C>(R.hist[ph]);
+    const gp<C> hout = gout<C>(R.hist[ph ^ 1]);
 
-    // phase 1: density (and psi) on the tile plus halo, raw moments on the tile
-    for (int p = threadIdx.x; p < RN; p += blockDim.x) {
+    // phase 1: density (and psi) on the tile plus halo, raw moments on the tile.  Each thread
+    // first issues the pull loads of all its positions so that they are in flight together, then
+    // corrects the positions next to the cylinder or on the inlet / outlet columns.
+    constexpr int IT1 = (RN + NT - 1) / NT;
+    C fv[IT1][9];
+    C Tv[IT1];
+    int rxv[IT1], ryv[IT1];
+    unsigned need = 0, solid = 0, inlet = 0;
+#pragma unroll
+    for (int j = 0; j < IT1; ++j) {
+        const int p = threadIdx.x + NT * j;
+        if (p >= RN) continue;
         const int lx = p % RW, ly = p / RW;
         const int gx = x0 - H + lx, gy = y0 - H + ly;
         const bool own = lx >= H && lx < H + TX && ly >= H && ly < H + TY && gx < nx && gy < ny;
         if (!fon && !own) continue;
         int rx, ry;
         const int kind = map_pos(R, gx, gy, rx, ry);
-        C rho, T;
+        rxv[j] = rx;
+        ryv[j] = ry;
+        need |= 1u << j;
+        if (kind == INLET_GHOST) inlet |= 1u << j;
         if (solid_at(R, rx, ry)) {
+            solid |= 1u << j;
+            continue;
+        }
+        pull_bulk<S, C>(R, K, fin, rx, ry, fv[j]);
+        Tv[j] = ld_at<C>(R.T[pt], (unsigned)(ry * P + rx));
+    }
+#pragma unroll
+    for (int j = 0; j < IT1; ++j) {
+        if (!((need >> j) & 1u)) continue;
+        const int p = threadIdx.x + NT * j;
+        const int lx = p % RW, ly = p / RW;
+        const int gx = x0 - H + lx, gy = y0 - H + ly;
+        const bool own = lx >= H && lx < H + TX && ly >= H && ly < H + TY && gx < nx && gy < ny;
+        const int rx = rxv[j], ry = ryv[j];
+        const int q = (ly - H) * TX + (lx - H);
+        C rho, T;
+        if ((solid >> j) & 1u) {
             rho = K.rho_w;
             T = K.T_w;
-            if (own) {
-                const int q = (ly - H) * TX + (lx - H);
-                s_m[0][q] = rho; s_m[1][q] = 0; s_m[2][q] = 0; s_m[3][q] = 0; s_m[4][q] = 0;
-            }
+            if (own) { s_m[0][q] = rho; s_m[1][q] = 0; s_m[2][q] = 0; s_m[3][q] = 0; s_m[4][q] = 0; }
         } else {
-            C f[9];
-            stream_node<S, C>(R, K, fin, hin, rx, ry, f);
+            C *f = fv[j];
+            if (near_cylinder(R, rx, ry) || (R.bc_x == 1 && (rx == 0 || rx == nx - 1))) {
+                const F9<C> sp = pull_special<S, C>(R, fin, R.hist[ph], rx, ry);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = sp.v[i];
+            }
             rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-            T = kind == INLET_GHOST ? K.T_sat : Tc[(size_t)ry * P + rx];
+            T = ((inlet >> j) & 1u) ? K.T_sat : Tv[j];
             if (own) {
-                const int q = (ly - H) * TX + (lx - H);
                 s_m[0][q] = rho;
                 s_m[1][q] = (f[1] - f[2]) + (f[5] - f[6]) + (f[7] - f[8]);
                 s_m[2][q] = (f[3] - f[4]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -275,51 +418,47 @@ __global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, co
     }
     __syncthreads();
 
-    C *__restrict__ orho = (C *)R.rho;
-    C *__restrict__ oux = (C *)R.ux;
-    C *__restrict__ ouy = (C *)R.uy;
-    const size_t plane = (size_t)ny * P;
-    const C cs2 = (C)(1.0 / 3.0);
+    const unsigned plane = (unsigned)ny * P;
 
     // phase 2: force, velocity, collision of the tile nodes
-    for (int q = threadIdx.x; q < TN; q += blockDim.x) {
+    for (int q = threadIdx.x; q < TN; q += NT) {
         const int lx = q % TX, ly = q / TX;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= nx || gy >= ny) continue;
-        const size_t idx = (size_t)gy * P + gx;
+        const unsigned idx = (unsigned)(gy * P + gx);
         if (solid_at(R, gx, gy)) {
-            orho[idx] = K.rho_w;
-            oux[idx] = 0;
-            ouy[idx] = 0;
+            *at<C>(R.rho, idx) = K.rho_w;
+            *at<C>(R.ux, idx) = 0;
+            *at<C>(R.uy, idx) = 0;
+            // never streamed from, but kept deterministic: the rest state of the wall density
+            if (WRITE_F) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    *(gp<RawT<S>>)(fout + ((unsigned)i * (unsigned)plane + (unsigned)idx) * (unsigned)sizeof(RawT<S>)) =
+                        Conv<S>::st((C)lat_w(i) * K.rho_w, K.shiftw[i]);
+            }
             continue;
         }
         const C rho = s_m[0][q], jx = s_m[1][q], jy = s_m[2][q], m4 = s_m[3][q], m5 = s_m[4][q];
         C Fx = 0, Fy = 0, A = 0;
         if (fon) {
             const int c = (ly + H) * RW + (lx + H);
-            C sx = 0, sy = 0;
-#pragma unroll
-            for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                for (int ex = -2; ex <= 2; ++ex) {
-                    if (ex == 0 && ey == 0) continue;
-                    const C w = (C)st_w(ex * ex + ey * ey);
-                    const C ps = s_psi[c + ey * RW + ex];
-                    sx += w * ps * (C)ex;
-                    sy += w * ps * (C)ey;
-                }
+            const PairD<C> d = pair_diffs<RW>(s_psi, c);
             const C psi0 = s_psi[c];
-            const C Fmx = -K.G * cs2 * psi0 * sx;
-            const C Fmy = -K.G * cs2 * psi0 * sy;
-            A = (C)2 * K.sigma * (Fmx * Fmx + Fmy * Fmy) / (psi0 * psi0);
+            // F_m = -G cs^2 psi sum_k w_k psi(x + e_k) e_k (eq. interForce); G cs^2 = 2/psi_scale
+            const C pre = -(C)2 * Ar<C>::rcp(K.psi_scale) * psi0;
+            const C Fmx = pre * d.gx();
+            const C Fmy = pre * d.gy();
+            A = (C)2 * K.sigma * (Fmx * Fmx + Fmy * Fmy) * Ar<C>::rcp(psi0 * psi0);
             Fx = Fmx + (rho - K.rho_gref) * K.gx;
             Fy = Fmy + (rho - K.rho_gref) * K.gy;
         }
-        const C U = (jx + (C)0.5 * Fx) / rho;
-        const C V = (jy + (C)0.5 * Fy) / rho;
-        orho[idx] = rho;
-        oux[idx] = U;
-        ouy[idx] = V;
+        const C ir = Ar<C>::rcp(rho);
+        const C U = (jx + (C)0.5 * Fx) * ir;
+        const C V = (jy + (C)0.5 * Fy) * ir;
+        *at<C>(R.rho, idx) = rho;
+        *at<C>(R.ux, idx) = U;
+        *at<C>(R.uy, idx) = V;
         if (!WRITE_F) continue;
 
         // pre-collision central moments k4, k5 from raw moments (rows 4, 5 of N(u))
@@ -329,8 +468,8 @@ __global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, co
         const C k0 = rho, k1 = (C)0.5 * Fx, k2 = (C)0.5 * Fy;
         const C k3 = (C)(2.0 / 3.0) * rho + A;
         const C k4s = ((C)1 - K.omega) * k4, k5s = ((C)1 - K.omega) * k5;
-        const C k6 = Fy / (C)6, k7 = Fx / (C)6;
-        const C k8 = rho / (C)9 + A / (C)3;
+        const C k6 = Fy * (C)(1.0 / 6.0), k7 = Fx * (C)(1.0 / 6.0);
+        const C k8 = rho * (C)(1.0 / 9.0) + A * (C)(1.0 / 3.0);
         // raw moments m* = N(-u) k*
         const C UU = U * U, VV = V * V, UV = U * V;
         const C r0 = k0;
@@ -343,9 +482,8 @@ __global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, co
         const C r7 = U * VV * k0 + VV * k1 + (C)2 * UV * k2 + (C)0.5 * U * (k3 - k4s) + (C)2 * V * k5s + k7;
         const C r8 = UU * VV * k0 + (C)2 * U * VV * k1 + (C)2 * UU * V * k2 + (C)0.5 * (UU + VV) * k3 -
                      (C)0.5 * (UU - VV) * k4s + (C)4 * UV * k5s + (C)2 * V * k6 + (C)2 * U * k7 + k8;
-        // populations f* = M^-1 m*
+        // populations f* = M^-1 m*; f*_0 closes the mass balance sum_i f*_i = k*_0 = rho exactly
         C fs[9];
-        fs[0] = r0 - r3 + r8;
         fs[1] = (C)0.5 * (r1 - r7 - r8) + (C)0.25 * (r3 + r4);
         fs[2] = (C)0.5 * (-r1 + r7 - r8) + (C)0.25 * (r3 + r4);
         fs[3] = (C)0.5 * (r2 - r6 - r8) + (C)0.25 * (r3 - r4);
@@ -354,147 +492,177 @@ __global__ __launch_bounds__(256) void k_lbm(const RunDev *__restrict__ runs, co
         fs[6] = (C)0.25 * (r5 - r6 - r7 + r8);
         fs[7] = (C)0.25 * (-r5 - r6 + r7 + r8);
         fs[8] = (C)0.25 * (-r5 + r6 - r7 + r8);
+        fs[0] = r0 - (((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8])));
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fout[(size_t)i * plane + idx] = Conv<S>::st(fs[i], K.shiftw[i]);
+        for (int i = 0; i < 9; ++i)
+            *(gp<RawT<S>>)(fout + ((unsigned)i * (unsigned)plane + (unsigned)idx) * (unsigned)sizeof(RawT<S>)) =
+                Conv<S>::st(fs[i], K.shiftw[i]);
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // k_thermal: Runge-Kutta update of the temperature equation (eq. energy) on an LDS tile
 // ------------------------------------------------------------------------------------------
-template <typename C, int TX, int TY, int NS>
-__global__ __launch_bounds__(256) void k_thermal(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt)
-{
-    constexpr int H = 2 * NS;  // frozen-field halo: 2 nodes per stage
-    constexpr int RW = TX + 2 * H, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
-    constexpr int MAXPT = (RN + 255) / 256;
-    __shared__ C s_ux[RN], s_uy[RN], s_T0[RN], s_Y[RN];  // s_Y holds rho until the invariants exist
-    __shared__ C s_gx[RN], s_gy[RN], s_c1[RN], s_c2[RN];
-    __shared__ C s_acc[TN];
+enum : unsigned char { F_SOLID = 1, F_INLET = 2, F_OUTLET = 4 };
 
-    const Tile t = tiles[blockIdx.x];
-    const RunDev &R = runs[t.run];
-    const Consts<C> K(R);
-    const int x0 = t.tx * TX, y0 = t.ty * TY;
-    const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const C *__restrict__ Tin = (const C *)R.T[pt];
-    C *__restrict__ Tout = (C *)R.T[pt ^ 1];
-    const C *__restrict__ grho = (const C *)R.rho;
-    const C *__restrict__ gux = (const C *)R.ux;
-    const C *__restrict__ guy = (const C *)R.uy;
+template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
+    static constexpr int H = 2 * NS;  // frozen-field halo: 2 nodes per stage
+    static constexpr int RW = TX + 2 * H, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
 
-    // load the frozen fields and T^n on the whole region
-    for (int p = threadIdx.x; p < RN; p += blockDim.x) {
-        const int lx = p % RW, ly = p / RW;
-        int rx, ry;
-        const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
-        const size_t idx = (size_t)ry * P + rx;
-        s_Y[p] = grho[idx];
-        s_ux[p] = gux[idx];
-        s_uy[p] = guy[idx];
-        s_T0[p] = kind == INLET_GHOST ? K.T_sat : Tin[idx];
-    }
-    for (int q = threadIdx.x; q < TN; q += blockDim.x) s_acc[q] = 0;
-    __syncthreads();
+    struct Smem {
+        C ux[RN], uy[RN], T0[RN], Y[RN];  // Y holds rho until the invariants exist
+        C gx[RN], gy[RN], c1[RN], c2[RN];
+        C acc[TN];
+        unsigned char flag[RN];
+    };
 
-    // stage-invariant coefficients on the region shrunk by 2:
-    //   gx, gy = alpha grad(rho)/rho;  c1 = -div(u) R rho/(1 - b rho) / (rho cv);
-    //   c2 = div(u) a rho^2/(1 + 2 b rho - b^2 rho^2) / (rho cv); source(T) = T (c1 + c2 phi'(T))
-    for (int p = threadIdx.x; p < RN; p += blockDim.x) {
-        const int lx = p % RW, ly = p / RW;
-        if (lx < 2 || lx >= RW - 2 || ly < 2 || ly >= RH - 2) continue;
-        C grx = 0, gry = 0, dv = 0;
+    // stage s of the Runge-Kutta update on the tile grown by 2 (NS - s) nodes
+    template <int s>
+    __device__ static void stage(Smem &sm, const Consts<C> &K, C cd, int out_c)
+    {
+        constexpr int m = 2 * (NS - s);
+        constexpr int W = TX + 2 * m, N = W * (TY + 2 * m);
+        constexpr int ITER = (N + NT - 1) / NT;
+        C kv[ITER];
 #pragma unroll
-        for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-            for (int ex = -2; ex <= 2; ++ex) {
-                if (ex == 0 && ey == 0) continue;
-                const C w = (C)st_w(ex * ex + ey * ey);
-                const int n = p + ey * RW + ex;
-                grx += w * s_Y[n] * (C)ex;
-                gry += w * s_Y[n] * (C)ey;
-                dv += w * (s_ux[n] * (C)ex + s_uy[n] * (C)ey);
-            }
-        const C rho = s_Y[p];
-        s_gx[p] = K.alpha * grx / rho;
-        s_gy[p] = K.alpha * gry / rho;
-        const C D = dv / (rho * K.cv);
-        s_c1[p] = -D * (rho * K.Rg / ((C)1 - K.b * rho));
-        s_c2[p] = D * (K.a * rho * rho / ((C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho));
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < RN; p += blockDim.x) s_Y[p] = s_T0[p];
-    __syncthreads();
-
-    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
-    for (int s = 1; s <= NS; ++s) {
-        const int m = 2 * (NS - s);  // region of this stage: tile grown by m
-        const int W = TX + 2 * m, Hh = TY + 2 * m, N = W * Hh;
-        C kv[MAXPT];
-#pragma unroll
-        for (int j = 0; j < MAXPT; ++j) {
+        for (int j = 0; j < ITER; ++j) {
             kv[j] = 0;
-            const int r = threadIdx.x + 256 * j;
+            const int r = threadIdx.x + NT * j;
             if (r >= N) continue;
             const int lx = H - m + r % W, ly = H - m + r / W;
-            int rx, ry;
-            const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
-            if (kind == INLET_GHOST || solid_at(R, rx, ry)) continue;
+            const unsigned char fl = sm.flag[ly * RW + lx];
+            if (fl & (F_SOLID | F_INLET)) continue;
             // an outlet ghost evaluates the operator at the last column of its row
-            const int cx = kind == OUTLET_GHOST ? lx - (x0 - H + lx - (nx - 1)) : lx;
-            const int c = ly * RW + cx;
-            const C y0v = s_Y[c];
-            const C u = s_ux[c], v = s_uy[c];
-            const C xm2 = s_Y[c - 2], xm1 = s_Y[c - 1], xp1 = s_Y[c + 1], xp2 = s_Y[c + 2];
-            const C ym2 = s_Y[c - 2 * RW], ym1 = s_Y[c - RW], yp1 = s_Y[c + RW], yp2 = s_Y[c + 2 * RW];
-            const C conv = u * (-xp2 + (C)8 * xp1 - (C)8 * xm1 + xm2) / (C)12 + fabs(u) * cd * (xp2 - (C)4 * xp1 + (C)6 * y0v - (C)4 * xm1 + xm2) +
-                           v * (-yp2 + (C)8 * yp1 - (C)8 * ym1 + ym2) / (C)12 + fabs(v) * cd * (yp2 - (C)4 * yp1 + (C)6 * y0v - (C)4 * ym1 + ym2);
-            C gxT = 0, gyT = 0, lap = 0;
-#pragma unroll
-            for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                for (int ex = -2; ex <= 2; ++ex) {
-                    if (ex == 0 && ey == 0) continue;
-                    const C w = (C)st_w(ex * ex + ey * ey);
-                    const C yn = s_Y[c + ey * RW + ex];
-                    gxT += w * yn * (C)ex;
-                    gyT += w * yn * (C)ey;
-                    lap += (C)2 * w * (yn - y0v);
-                }
-            const C diff = K.alpha * lap + s_gx[c] * gxT + s_gy[c] * gyT;
-            // phi'(T) = -kappa (1 + kappa (1 - sqrt(T/Tc))) / sqrt(T Tc)
-            const C sq = sqrt(y0v / K.Tc);
-            const C dphi = -K.kappa * ((C)1 + K.kappa * ((C)1 - sq)) / sqrt(y0v * K.Tc);
-            const C src = y0v * (s_c1[c] + s_c2[c] * dphi);
-            kv[j] = -conv + diff + src;
+            const int c = ly * RW + ((fl & F_OUTLET) ? out_c : lx);
+            const C *Y = sm.Y;
+            const C y0 = Y[c];
+            // sums and differences of opposite neighbours
+            const C p10 = Y[c + 1], m10 = Y[c - 1], p20 = Y[c + 2], m20 = Y[c - 2];
+            const C p01 = Y[c + RW], m01 = Y[c - RW], p02 = Y[c + 2 * RW], m02 = Y[c - 2 * RW];
+            const C S10 = p10 + m10, S20 = p20 + m20, S01 = p01 + m01, S02 = p02 + m02;
+            PairD<C> d;
+            d.d10 = p10 - m10; d.d20 = p20 - m20; d.d01 = p01 - m01; d.d02 = p02 - m02;
+            const C a11 = Y[c + RW + 1], b11 = Y[c - RW - 1], a1m = Y[c - RW + 1], b1m = Y[c + RW - 1];
+            const C a21 = Y[c + RW + 2], b21 = Y[c - RW - 2], a2m = Y[c - RW + 2], b2m = Y[c + RW - 2];
+            const C a12 = Y[c + 2 * RW + 1], b12 = Y[c - 2 * RW - 1], a1m2 = Y[c - 2 * RW + 1], b1m2 = Y[c + 2 * RW - 1];
+            const C a22 = Y[c + 2 * RW + 2], b22 = Y[c - 2 * RW - 2], a2m2 = Y[c - 2 * RW + 2], b2m2 = Y[c + 2 * RW - 2];
+            d.d11 = a11 - b11; d.d1m = a1m - b1m; d.d21 = a21 - b21; d.d2m = a2m - b2m;
+            d.d12 = a12 - b12; d.d1m2 = a1m2 - b1m2; d.d22 = a22 - b22; d.d2m2 = a2m2 - b2m2;
+            // isotropic Laplacian 2 sum_k w_k (Y(x + e_k) - Y(x))
+            const C lap = (C)2 * ((C)W1 * (S10 + S01) + (C)W2 * ((a11 + b11) + (a1m + b1m)) + (C)W4 * (S20 + S02) +
+                                  (C)W5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
+                                  (C)W8 * ((a22 + b22) + (a2m2 + b2m2))) -
+                          (C)(2.0 * WSUM) * y0;
+            // third-order upwind-biased convection
+            const C u = sm.ux[c], v = sm.uy[c];
+            const C conv = u * ((C)8 * d.d10 - d.d20) * (C)(1.0 / 12.0) + fabs(u) * cd * (S20 - (C)4 * S10 + (C)6 * y0) +
+                           v * ((C)8 * d.d01 - d.d02) * (C)(1.0 / 12.0) + fabs(v) * cd * (S02 - (C)4 * S01 + (C)6 * y0);
+            const C diff = K.alpha * lap + sm.gx[c] * d.gx() + sm.gy[c] * d.gy();
+            // pressure-work source T (c1 + c2 phi'(T)) with phi'(T) = A / sqrt(T) + B
+            const C src = sm.c1[c] * y0 + sm.c2[c] * Ar<C>::sqrt_(y0);
+            kv[j] = diff + src - conv;
         }
         __syncthreads();  // every stage input has been read
 #pragma unroll
-        for (int j = 0; j < MAXPT; ++j) {
-            const int r = threadIdx.x + 256 * j;
+        for (int j = 0; j < ITER; ++j) {
+            const int r = threadIdx.x + NT * j;
             if (r >= N) continue;
             const int lx = H - m + r % W, ly = H - m + r / W;
             const int c = ly * RW + lx;
             const bool in_tile = lx >= H && lx < H + TX && ly >= H && ly < H + TY;
             const int q = (ly - H) * TX + (lx - H);
             const C k = kv[j];
-            if (NS == 4) {
-                if (s == 1) { if (in_tile) s_acc[q] = k; s_Y[c] = s_T0[c] + (C)0.5 * k; }
-                else if (s == 2) { if (in_tile) s_acc[q] += (C)2 * k; s_Y[c] = s_T0[c] + (C)0.5 * k; }
-                else if (s == 3) { if (in_tile) s_acc[q] += (C)2 * k; s_Y[c] = s_T0[c] + k; }
-                else { if (in_tile) s_acc[q] = s_T0[c] + (s_acc[q] + k) / (C)6; }
+            if constexpr (NS == 4) {
+                if constexpr (s == 1) { if (in_tile) sm.acc[q] = k; sm.Y[c] = sm.T0[c] + (C)0.5 * k; }
+                else if constexpr (s == 2) { if (in_tile) sm.acc[q] += (C)2 * k; sm.Y[c] = sm.T0[c] + (C)0.5 * k; }
+                else if constexpr (s == 3) { if (in_tile) sm.acc[q] += (C)2 * k; sm.Y[c] = sm.T0[c] + k; }
+                else { if (in_tile) sm.acc[q] = sm.T0[c] + (sm.acc[q] + k) * (C)(1.0 / 6.0); }
             } else {
-                if (s == 1) { if (in_tile) s_acc[q] = k; s_Y[c] = s_T0[c] + k; }
-                else { if (in_tile) s_acc[q] = s_T0[c] + (C)0.5 * (s_acc[q] + k); }
+                if constexpr (s == 1) { if (in_tile) sm.acc[q] = k; sm.Y[c] = sm.T0[c] + k; }
+                else { if (in_tile) sm.acc[q] = sm.T0[c] + (C)0.5 * (sm.acc[q] + k); }
             }
         }
         __syncthreads();
     }
+};
 
-    for (int q = threadIdx.x; q < TN; q += blockDim.x) {
+template <typename C, int TX, int TY, int NS, int NT>
+__global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt,
+                                                long long step)
+{
+    using Th = Thermal<C, TX, TY, NS, NT>;
+    constexpr int H = Th::H, RW = Th::RW, RH = Th::RH, RN = Th::RN, TN = Th::TN;
+    __shared__ typename Th::Smem sm;
+
+    const Tile t = tiles[blockIdx.x];
+    const RunDev &R = runs[t.run];
+    const int x0 = t.tx * TX, y0 = t.ty * TY;
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    const gp<const C> Tin = gin<C>(R.T[pt]);
+    const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
+    if (step < R.warmup || R.rk == 0) {
+        // this run does not advance its temperature in this step: carry T over
+        for (int q = threadIdx.x; q < TN; q += NT) {
+            const int gx = x0 + q % TX, gy = y0 + q / TX;
+            if (gx < nx && gy < ny) Tout[(size_t)gy * P + gx] = Tin[(size_t)gy * P + gx];
+        }
+        return;
+    }
+    const Consts<C> K(R);
+
+    // load the frozen fields and T^n on the whole region
+    for (int p = threadIdx.x; p < RN; p += NT) {
+        const int lx = p % RW, ly = p / RW;
+        int rx, ry;
+        const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        const unsigned idx = (unsigned)(ry * P + rx);
+        sm.Y[p] = ld_at<C>(R.rho, idx);
+        sm.ux[p] = ld_at<C>(R.ux, idx);
+        sm.uy[p] = ld_at<C>(R.uy, idx);
+        sm.T0[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
+        sm.flag[p] = (unsigned char)((solid_at(R, rx, ry) ? F_SOLID : 0) | (kind == INLET_GHOST ? F_INLET : 0) |
+                                     (kind == OUTLET_GHOST ? F_OUTLET : 0));
+    }
+    __syncthreads();
+
+    // stage-invariant coefficients on the region shrunk by 2:
+    //   gx, gy = alpha grad(rho)/rho;  source(T) = c1 T + c2 sqrt(T) with
+    //   D = div(u)/(rho cv), c1 = -D R rho/(1 - b rho) + B D a rho^2/(1 + 2 b rho - b^2 rho^2),
+    //   c2 = A D a rho^2/(1 + 2 b rho - b^2 rho^2), phi'(T) = A/sqrt(T) + B
+    for (int p = threadIdx.x; p < RN; p += NT) {
+        const int lx = p % RW, ly = p / RW;
+        if (lx < 2 || lx >= RW - 2 || ly < 2 || ly >= RH - 2) continue;
+        const PairD<C> dr = pair_diffs<RW>(sm.Y, p);
+        const PairD<C> du = pair_diffs<RW>(sm.ux, p);
+        const PairD<C> dv = pair_diffs<RW>(sm.uy, p);
+        const C rho = sm.Y[p];
+        const C ir = Ar<C>::rcp(rho);
+        sm.gx[p] = K.alpha * dr.gx() * ir;
+        sm.gy[p] = K.alpha * dr.gy() * ir;
+        const C D = (du.gx() + dv.gy()) * ir * K.inv_cv;
+        const C d1 = (C)1 - K.b * rho;
+        const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
+        const C A2 = D * K.a * rho * rho * Ar<C>::rcp(d2);
+        sm.c1[p] = -D * rho * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
+        sm.c2[p] = K.dphi_A * A2;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < RN; p += NT) sm.Y[p] = sm.T0[p];
+    __syncthreads();
+
+    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
+    const int out_c = (nx - 1) - (x0 - H);  // LDS column of the last domain column
+    Th::template stage<1>(sm, K, cd, out_c);
+    Th::template stage<2>(sm, K, cd, out_c);
+    if constexpr (NS == 4) {
+        Th::template stage<3>(sm, K, cd, out_c);
+        Th::template stage<4>(sm, K, cd, out_c);
+    }
+
+    for (int q = threadIdx.x; q < TN; q += NT) {
         const int gx = x0 + q % TX, gy = y0 + q / TX;
         if (gx >= nx || gy >= ny) continue;
-        Tout[(size_t)gy * P + gx] = solid_at(R, gx, gy) ? K.T_w : s_acc[q];
+        *at<C>(R.T[pt ^ 1], (unsigned)(gy * P + gx)) = solid_at(R, gx, gy) ? K.T_w : sm.acc[q];
     }
 }
 
@@ -505,7 +673,7 @@ template <typename C>
 __global__ __launch_bounds__(256) void k_diag_partial(const RunDev *__restrict__ runs, int run)
 {
     const RunDev &R = runs[run];
-    const C *__restrict__ rho = (const C *)R.rho;
+    const gp<const C> rho = gin<C>(R.rho);
     __shared__ double red[256];
     double s = 0.0;
     const long long n = (long long)R.nx * R.ny;
@@ -526,8 +694,8 @@ template <typename C>
 __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ runs, int run, int pt, int accumulate)
 {
     const RunDev &R = runs[run];
-    const C *__restrict__ rho = (const C *)R.rho;
-    const C *__restrict__ T = (const C *)R.T[pt];
+    const gp<const C> rho = gin<C>(R.rho);
+    const gp<const C> T = gin<C>(R.T[pt]);
     __shared__ double qp[kMaxProbes];
     for (int k = threadIdx.x; k < R.np; k += 256) {
         const double px = R.probes[2 * k], py = R.probes[2 * k + 1];
@@ -572,7 +740,7 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
     // host-provided fields were uploaded into rho, ux, uy and T[0]
     const C *rho = (const C *)R.rho, *ux = (const C *)R.ux, *uy = (const C *)R.uy;
     C *T = (C *)R.T[0];
-    S *f = (S *)R.f[0];
+    RawT<S> *f = (RawT<S> *)R.f[0];
     C *hist = (C *)R.hist[0];
     const size_t plane = (size_t)R.ny * R.pitch;
     const long long n = (long long)R.nx * R.ny;
@@ -607,63 +775,102 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-// Launchers
+// Launch variants (tile shape, threads per block) and launchers
 // ------------------------------------------------------------------------------------------
-TileShape tile_shape(int precision, int rk)
+// stream+collide: FP32 and reduced-precision storage / FP64
+static const Variant kLbm32[] = {{32, 16, 256}, {64, 16, 512}, {32, 32, 512}, {32, 8, 256}};
+static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
+// temperature update (LDS holds 8 fields of the tile grown by 2 nodes per stage)
+static const Variant kTh32[] = {{32, 32, 512}, {32, 16, 256}, {64, 32, 512}, {16, 16, 256}};
+static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
+
+int variant_count(int precision, int kernel)
 {
-    (void)rk;
-    if (precision == 0) return TileShape{32, 16, 16, 16};
-    return TileShape{32, 16, 32, 32};
+    if (kernel == 0) return precision == 0 ? 2 : 4;
+    return precision == 0 ? 2 : 4;
 }
 
-template <typename S>
-static hipError_t lbm_impl(bool write_f, const RunDev *runs, const Tile *tiles, int n, int pf, int pt, int ph,
-                           long long step, hipStream_t st, int tx, int ty)
+Variant variant_shape(int precision, int kernel, int v)
 {
-    if (n <= 0) return hipSuccess;
-    if (tx == 32 && ty == 16) {
-        if (write_f) k_lbm<S, 32, 16, true><<<n, 256, 0, st>>>(runs, tiles, pf, pt, ph, step);
-        else k_lbm<S, 32, 16, false><<<n, 256, 0, st>>>(runs, tiles, pf, pt, ph, step);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0};
+    if (kernel == 0) return precision == 0 ? kLbm64[v] : kLbm32[v];
+    return precision == 0 ? kTh64[v] : kTh32[v];
+}
+
+template <typename S, int TX, int TY, int NT>
+static hipError_t lbm_go(bool write_f, const RunDev *runs, const Tile *tiles, int n, int pf, int pt, int ph,
+                         long long step, hipStream_t st)
+{
+    if (write_f) k_lbm<S, TX, TY, NT, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    else k_lbm<S, TX, TY, NT, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
     return hipGetLastError();
 }
 
-hipError_t launch_lbm(int precision, bool write_f, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int pf,
-                      int pt, int ph, long long step, hipStream_t stream)
+template <typename S>
+static hipError_t lbm_impl(int v, bool write_f, const RunDev *runs, const Tile *tiles, int n, int pf, int pt, int ph,
+                           long long step, hipStream_t st)
 {
-    const TileShape ts = tile_shape(precision, 4);
+    if (n <= 0) return hipSuccess;
+    if constexpr (std::is_same<S, double>::value) {
+        switch (v) {
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 1: return lbm_go<S, 16, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (v) {
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 1: return lbm_go<S, 64, 16, 512>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 2: return lbm_go<S, 32, 32, 512>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 3: return lbm_go<S, 32, 8, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+hipError_t launch_lbm(int precision, int variant, bool write_f, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                      int pf, int pt, int ph, long long step, hipStream_t stream)
+{
     switch (precision) {
-    case 0: return lbm_impl<double>(write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, ts.lbm_tx, ts.lbm_ty);
-    case 1: return lbm_impl<float>(write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, ts.lbm_tx, ts.lbm_ty);
-    case 2: return lbm_impl<__half>(write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, ts.lbm_tx, ts.lbm_ty);
-    case 3: return lbm_impl<__hip_bfloat16>(write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, ts.lbm_tx, ts.lbm_ty);
+    case 0: return lbm_impl<double>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 1: return lbm_impl<float>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 2: return lbm_impl<__half>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_thermal(int precision, int rk, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int pt,
-                          long long step, hipStream_t stream)
+template <typename C, int TX, int TY, int NT>
+static hipError_t th_go(int rk, const RunDev *runs, const Tile *tiles, int n, int pt, long long step, hipStream_t st)
 {
-    (void)step;
-    if (n_tiles <= 0) return hipSuccess;
-    if (precision == 0) {
-        if (rk == 4) k_thermal<double, 16, 16, 4><<<n_tiles, 256, 0, stream>>>(runs_dev, tiles, pt);
-        else if (rk == 2) k_thermal<double, 16, 16, 2><<<n_tiles, 256, 0, stream>>>(runs_dev, tiles, pt);
-        else return hipErrorInvalidValue;
-    } else {
-        if (rk == 4) k_thermal<float, 32, 32, 4><<<n_tiles, 256, 0, stream>>>(runs_dev, tiles, pt);
-        else if (rk == 2) k_thermal<float, 32, 32, 2><<<n_tiles, 256, 0, stream>>>(runs_dev, tiles, pt);
-        else return hipErrorInvalidValue;
-    }
+    if (rk == 4) k_thermal<C, TX, TY, 4, NT><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+    else if (rk == 2) k_thermal<C, TX, TY, 2, NT><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, const RunDev &host_run, int pt, int accumulate,
-                       hipStream_t stream)
+hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                          int pt, long long step, hipStream_t stream)
 {
-    (void)host_run;
+    if (n_tiles <= 0) return hipSuccess;
+    if (precision == 0) {
+        switch (variant) {
+        case 0: return th_go<double, 16, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+        case 1: return th_go<double, 32, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (variant) {
+    case 0: return th_go<float, 32, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 1: return th_go<float, 32, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 2: return th_go<float, 64, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 3: return th_go<float, 16, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int pt, int accumulate, hipStream_t stream)
+{
     if (precision == 0) {
         k_diag_partial<double><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
         k_diag_final<double><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
@@ -674,10 +881,9 @@ hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, const Run
     return hipGetLastError();
 }
 
-hipError_t launch_init(int precision, const RunDev *runs_dev, int run, const RunDev &host_run, hipStream_t stream)
+hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream)
 {
-    const long long n = (long long)host_run.nx * host_run.ny;
-    int blocks = (int)((n + 255) / 256);
+    int blocks = (int)((nodes + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     switch (precision) {
     case 0: k_init<double><<<blocks, 256, 0, stream>>>(runs_dev, run); break;

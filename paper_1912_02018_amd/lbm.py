@@ -35,7 +35,10 @@ EXPORTED = [
     "lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_fields", "lbm_set_fields",
     "lbm_get_state", "lbm_set_state", "lbm_wall_heat_flux", "lbm_total_mass", "lbm_derived",
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
+    "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
+    "lbm_set_option",
 ]
+OPT_GRAPHS = 0
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
 
 
@@ -76,6 +79,13 @@ def load_library():
     L.lbm_total_mass.argtypes = [vp, i32, dp]
     L.lbm_derived.argtypes = [vp, i32, dp]
     L.lbm_time_kernel.argtypes = [vp, i32, i32]
+    ip = C.POINTER(C.c_int)
+    L.lbm_variant_count.argtypes = [i32, i32]
+    L.lbm_variant_shape.argtypes = [i32, i32, i32, ip, ip, ip]
+    L.lbm_set_variant.argtypes = [vp, i32, i32]
+    L.lbm_get_variant.argtypes = [vp, i32]
+    L.lbm_autotune.argtypes = [vp, i32, ip]
+    L.lbm_set_option.argtypes = [vp, i32, i32]
     L.lbm_step_count.argtypes = [vp]
     L.lbm_step_count.restype = i64
     L.lbm_last_error.argtypes = [vp]
@@ -162,6 +172,31 @@ class Simulation:
     def time_kernel(self, kernel: int, n: int):
         """Enqueue n launches of one kernel of the step without advancing the state."""
         self._check(self._L.lbm_time_kernel(self.h, int(kernel), int(n)))
+
+    def variants(self, kernel: int):
+        """(tx, ty, threads) of every launch variant of a kernel (0 k_lbm, 1 k_thermal)."""
+        prec = self.cfgs[0].precision
+        out = []
+        for v in range(self._L.lbm_variant_count(prec, kernel)):
+            a, b, c = C.c_int(), C.c_int(), C.c_int()
+            self._L.lbm_variant_shape(prec, kernel, v, C.byref(a), C.byref(b), C.byref(c))
+            out.append((a.value, b.value, c.value))
+        return out
+
+    def set_variant(self, kernel: int, variant: int):
+        self._check(self._L.lbm_set_variant(self.h, int(kernel), int(variant)))
+
+    def get_variant(self, kernel: int) -> int:
+        return int(self._L.lbm_get_variant(self.h, int(kernel)))
+
+    def autotune(self, launches: int = 20):
+        """Time every launch variant of both kernels on the current state; keep the fastest."""
+        best = (C.c_int * 2)()
+        self._check(self._L.lbm_autotune(self.h, int(launches), best))
+        return best[0], best[1]
+
+    def set_graphs(self, enabled: bool):
+        self._check(self._L.lbm_set_option(self.h, OPT_GRAPHS, 1 if enabled else 0))
 
     def set_fields(self, rho, ux, uy, T=None, run: int = 0):
         shp = self._shape(run)

@@ -85,9 +85,11 @@ def test_flat_interface_fp64(lbm_mod, steps):
     sim, ref = run_pair(lbm_mod, cfg, steps, (rho, 0.0, 0.0))
     # rounding-order differences accumulate about linearly: 1e-12 per 1000 steps
     compare(sim, ref, f"flat interface 128x64 {steps} steps", tol=TOL64 * steps / 1000)
+    # the GPU step closes the mass balance node by node: its total mass is constant to rounding;
+    # the oracle's own drift (LU rounding, pinned at < 1e-12 over 2000 steps) bounds the gap
     m_g, m_o = sim.total_mass(), ref.total_mass()
-    assert abs(m_g / m_o - 1) < 1e-13
-    assert abs(m_g / (rho.sum()) - 1) < 1e-12
+    assert abs(m_g / rho.sum() - 1) < 1e-13
+    assert abs(m_g / m_o - 1) < 1e-12
 
 
 def cylinder_case(nx=128, ny=64, r=8, cx=40, re=100.0, rk=4, precision=FP64, **kw):
@@ -187,3 +189,53 @@ def test_fp32_error_after_1000_steps(lbm_mod):
     sim.step(1000)
     ref.step(1000)
     compare(sim, ref, "fp32 vs oracle cylinder 1000 steps", tol=1e-4, tol_u=1e-3, u_ref=cfg32.u_in)
+
+
+def test_graph_replay_matches_eager_bitwise(lbm_mod):
+    """Steps replayed from captured HIP graphs equal directly launched steps bit for bit, over
+    several replays separated by eager work (field read-back, heat-flux reductions)."""
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32)
+    a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
+    b.set_graphs(False)
+    for chunk in (7, 40, 25, 100, 3, 60):
+        a.step(chunk)
+        b.step(chunk)
+        fa, fb = a.fields(), b.fields()
+        assert all(np.array_equal(fa[k], fb[k]) for k in ("rho", "ux", "uy", "T")), chunk
+        assert a.wall_heat_flux() == b.wall_heat_flux()
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
+
+
+@pytest.mark.parametrize("precision", [FP32, FP64])
+def test_launch_variants_agree(lbm_mod, precision):
+    """Every tile shape of both stencil kernels gives the same state bit for bit (the per-node
+    arithmetic does not depend on the tile); FP64 variants also match the oracle."""
+    cfg = cylinder_case(nx=100, ny=50, r=6, cx=30, precision=precision)
+    ref_state = None
+    probe = lbm_mod.Simulation(cfg)
+    nl, nt = len(probe.variants(0)), len(probe.variants(1))
+    for vl in range(nl):
+        for vt in range(nt):
+            sim = lbm_mod.Simulation(cfg)
+            sim.set_variant(0, vl)
+            sim.set_variant(1, vt)
+            sim.step(120)
+            st = sim.get_state()[:3]
+            if ref_state is None:
+                ref_state = st
+                if precision == FP64:
+                    ref = oracle.Sim(cfg)
+                    ref.step(120)
+                    compare(sim, ref, f"variants lbm {vl} thermal {vt}", u_ref=cfg.u_in)
+            else:
+                assert all(np.array_equal(x, y) for x, y in zip(st, ref_state)), (vl, vt)
+
+
+def test_autotune_keeps_results(lbm_mod):
+    cfg = cylinder_case(nx=128, ny=64, precision=FP32)
+    a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
+    best = a.autotune(5)
+    assert a.get_variant(0) == best[0] and a.get_variant(1) == best[1]
+    a.step(50)
+    b.step(50)
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
