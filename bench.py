@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# Algorithmic traffic / work per lattice update of each kernel of the step (see DESIGN.md):
+# Algorithmic traffic / work per lattice update of each kernel of the step:
 #   stream+collide: read 9 populations, write 9 populations, read T (psi)       -> 19 values
 #   temperature:    read T^n, write T^{n+1}                                       ->  2 values
 #   temperature useful flops: 4 stages x ~150 + ~130 stage-invariant             -> 730 flops
@@ -103,8 +103,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the boiling step is not split across GPUs in this build "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: a boiling run is not split across GPUs (the step would "
+              "shard as x-slabs with halo exchange, the sweep by runs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

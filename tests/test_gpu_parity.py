@@ -46,7 +46,7 @@ def rel(a, b):
 
 def compare(sim, ref, label, tol=TOL64, tol_u=None, u_ref=0.01, run=0):
     """Relative max-norm differences of rho, T and the populations f*; velocity as a vector,
-    relative to max(||u||_inf, u_ref) so that a flow decaying towards rest is not judged against
+    relative to max(||u||_inf, u_ref) so that a flow decaying towards rest is not measured against
     its own vanishing scale (u_ref = inlet velocity for channels, 0.01 otherwise)."""
     g, o = sim.fields(run), ref.fields()
     assert np.array_equal(g["mask"], o["mask"])
