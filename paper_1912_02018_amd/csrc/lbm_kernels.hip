@@ -183,22 +183,26 @@ __device__ inline double link_q(const RunDev &R, int x, int y, int i)
 }
 
 // Plain pulls of a node away from the cylinder; at the inlet / outlet columns the sources outside
-// the domain are clamped in (their values are replaced by apply_x_bc).
+// the domain are clamped in (their values are replaced by apply_x_bc).  Offsets are formed once per
+// node: one row product, neighbouring rows and columns by adds and selects.
 template <typename S, typename C>
 __device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
+    constexpr unsigned es = (unsigned)sizeof(RawT<S>);
     const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const unsigned plane = (unsigned)ny * P;
+    const unsigned rowB = (unsigned)P * es, planeB = (unsigned)ny * rowB;
     const bool periodic = R.bc_x == 0;
-    const int ym = y == 0 ? ny - 1 : y - 1;
-    const int yp = y == ny - 1 ? 0 : y + 1;
-    const int xm = x == 0 ? (periodic ? nx - 1 : 0) : x - 1;
-    const int xp = x == nx - 1 ? (periodic ? 0 : nx - 1) : x + 1;
+    const unsigned r0 = (unsigned)y * rowB;
+    const unsigned rm = y == 0 ? r0 + planeB - rowB : r0 - rowB;
+    const unsigned rp = y == ny - 1 ? r0 + rowB - planeB : r0 + rowB;
+    const unsigned c0 = (unsigned)x * es;
+    const unsigned cm = x == 0 ? (periodic ? (unsigned)(nx - 1) * es : 0u) : c0 - es;
+    const unsigned cp = x == nx - 1 ? (periodic ? 0u : c0) : c0 + es;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const int xs = cx_of(i) > 0 ? xm : (cx_of(i) < 0 ? xp : x);
-        const int ys = cy_of(i) > 0 ? ym : (cy_of(i) < 0 ? yp : y);
-        f[i] = ldf<S, C>(fin, plane, P, i, xs, ys, K);
+        const unsigned row = cy_of(i) > 0 ? rm : (cy_of(i) < 0 ? rp : r0);
+        const unsigned col = cx_of(i) > 0 ? cm : (cx_of(i) < 0 ? cp : c0);
+        f[i] = Conv<S>::ld(*(gp<const RawT<S>>)(fin + ((unsigned)i * planeB + row + col)), K.shiftw[i]);
     }
 }
 
