@@ -49,13 +49,14 @@ def source_digest() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_name: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this source."""
+def measured_traffic(variant: str, workload: str):
+    """HBM-side bytes per launch of one launch variant (FETCH_SIZE and WRITE_SIZE of committed
+    rocprofv3 counter runs, scaled by the same counters on a plain copy), if taken on this source."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
-        rec = json.load(open(p)).get(f"{kernel_name}@{workload}")
+        rec = json.load(open(p)).get(f"{variant}@{workload}")
     except (OSError, ValueError):
         return None
     if not rec or rec.get("source_sha") != source_digest():
@@ -161,18 +162,20 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
         kt[k] = e0.elapsed_time(e1) / launches  # ms per launch
     dom = max(kt, key=kt.get)
     name = KERNEL_NAMES[dom]
+    tx, ty, nt = sim.variants(dom)[sim.get_variant(dom)][:3]
+    variant = f"{name}<{tx}x{ty}x{nt}>" if dom == 0 else f"{name}<{tx}x{ty}x{nt},rk{cfg.rk_stages}>"
     if dom == 0:
         per_launch = kernel_bytes_per_lup(0, prec) * nodes
         achieved = per_launch / (kt[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(variant, workload)}
     else:
         flops = THERMAL_FLOPS_PER_LUP[cfg.rk_stages] * nodes
         achieved = flops / (kt[dom] * 1e-3) / 1e12
         peak = FP64_VECTOR_PEAK_TFLOPS if prec == 0 else FP32_VECTOR_PEAK_TFLOPS
         roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(name, workload)}
-    roof["kernel"] = name
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(variant, workload)}
+    roof["kernel"] = variant
     roof["kernel_ms"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in kt.items()}
     roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
                               for k, v in kt.items()}
