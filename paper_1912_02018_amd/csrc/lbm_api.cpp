@@ -429,6 +429,11 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         R.eos_a = k.eos_a; R.eos_b = k.eos_b; R.eos_R = k.eos_R;
         R.u_in = k.u_in; R.alpha = k.alpha_T; R.cv = k.cv;
         R.shift = prec >= 2 ? k.rho_ref_shift : 0.0;
+        R.inv_sqrt_Tc = 1.0 / std::sqrt(R.Tc);
+        R.psi_scale = 2.0 / (R.G * (1.0 / 3.0));
+        R.dphi_A = -R.kappa * (1.0 + R.kappa) / std::sqrt(R.Tc);
+        R.dphi_B = R.kappa * R.kappa / R.Tc;
+        R.inv_cv = 1.0 / R.cv;
 
         unsigned char *p = ws + L.run_off[r];
         const size_t plane = (size_t)R.ny * R.pitch;

@@ -25,6 +25,8 @@ struct RunDev {
     double omega, sigma, G, gx, gy, rho_gref, rho_w, rho_l, rho_v;
     double T_sat, T_w, Tc, kappa, eos_a, eos_b, eos_R;
     double u_in, alpha, cv, shift;
+    // derived on the host: 1/sqrt(Tc), 2/(G cs^2), phi'(T) = dphi_A/sqrt(T) + dphi_B, 1/cv
+    double inv_sqrt_Tc, psi_scale, dphi_A, dphi_B, inv_cv;
     void *f[2];               // populations, storage type, [9][ny][pitch]
     void *T[2];               // temperature, compute type, [ny][pitch]
     void *rho, *ux, *uy;      // macroscopic fields of the last streamed state, compute type

@@ -96,8 +96,11 @@ template <typename S> using CT = typename std::conditional<std::is_same<S, doubl
 // periodic wrap of a coordinate (halos may span several periods of a tiny grid)
 __device__ inline int wrap(int a, int n)
 {
-    while (a < 0) a += n;
-    while (a >= n) a -= n;
+    a = a < 0 ? a + n : (a >= n ? a - n : a);
+    if ((unsigned)a >= (unsigned)n) {
+        while (a < 0) a += n;
+        while (a >= n) a -= n;
+    }
     return a;
 }
 
@@ -137,12 +140,12 @@ template <typename C> struct Consts {
         omega = (C)R.omega; sigma = (C)R.sigma; gx = (C)R.gx; gy = (C)R.gy;
         rho_gref = (C)R.rho_gref; rho_w = (C)R.rho_w; T_sat = (C)R.T_sat; T_w = (C)R.T_w;
         a = (C)R.eos_a; b = (C)R.eos_b; Rg = (C)R.eos_R; u_in = (C)R.u_in;
-        alpha = (C)R.alpha; inv_cv = (C)(1.0 / R.cv); kappa = (C)R.kappa;
-        inv_sqrt_Tc = (C)(1.0 / sqrt(R.Tc));
-        psi_scale = (C)(2.0 / (R.G * (1.0 / 3.0)));
+        alpha = (C)R.alpha; inv_cv = (C)R.inv_cv; kappa = (C)R.kappa;
+        inv_sqrt_Tc = (C)R.inv_sqrt_Tc;
+        psi_scale = (C)R.psi_scale;
         // phi'(T) = dphi_A / sqrt(T) + dphi_B
-        dphi_A = (C)(-R.kappa * (1.0 + R.kappa) / sqrt(R.Tc));
-        dphi_B = (C)(R.kappa * R.kappa / R.Tc);
+        dphi_A = (C)R.dphi_A;
+        dphi_B = (C)R.dphi_B;
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
@@ -294,6 +297,14 @@ __device__ __attribute__((noinline)) F9<C> pull_special(const RunDev &R, const c
     return r;
 }
 
+// An index the optimiser cannot re-associate with the constant offsets added to it afterwards,
+// so that a 5x5 LDS window is read with one base register and immediate offsets.
+__device__ inline int opaque_index(int i)
+{
+    asm volatile("" : "+v"(i));
+    return i;
+}
+
 // x and y components of sum_k w_k a(x + e_k) e_k from the differences of opposite neighbours
 template <typename C> struct PairD {
     C d10, d01, d11, d1m, d20, d02, d21, d2m, d12, d1m2, d22, d2m2;
@@ -310,21 +321,26 @@ template <typename C> struct PairD {
 };
 
 // differences of opposite neighbours of LDS position c in a row-major array of row stride RW
+// (addressed from the lowest corner of the 5x5 window so that every read is a positive offset
+// from one base address)
 template <int RW, typename C> __device__ inline PairD<C> pair_diffs(const C *s, int c)
 {
+    const C *b = s + opaque_index(c - 2 * RW - 2);
+#define W_(dx, dy) b[(2 + (dy)) * RW + 2 + (dx)]
     PairD<C> d;
-    d.d10 = s[c + 1] - s[c - 1];
-    d.d01 = s[c + RW] - s[c - RW];
-    d.d11 = s[c + RW + 1] - s[c - RW - 1];
-    d.d1m = s[c - RW + 1] - s[c + RW - 1];
-    d.d20 = s[c + 2] - s[c - 2];
-    d.d02 = s[c + 2 * RW] - s[c - 2 * RW];
-    d.d21 = s[c + RW + 2] - s[c - RW - 2];
-    d.d2m = s[c - RW + 2] - s[c + RW - 2];
-    d.d12 = s[c + 2 * RW + 1] - s[c - 2 * RW - 1];
-    d.d1m2 = s[c - 2 * RW + 1] - s[c + 2 * RW - 1];
-    d.d22 = s[c + 2 * RW + 2] - s[c - 2 * RW - 2];
-    d.d2m2 = s[c - 2 * RW + 2] - s[c + 2 * RW - 2];
+    d.d10 = W_(1, 0) - W_(-1, 0);
+    d.d01 = W_(0, 1) - W_(0, -1);
+    d.d11 = W_(1, 1) - W_(-1, -1);
+    d.d1m = W_(1, -1) - W_(-1, 1);
+    d.d20 = W_(2, 0) - W_(-2, 0);
+    d.d02 = W_(0, 2) - W_(0, -2);
+    d.d21 = W_(2, 1) - W_(-2, -1);
+    d.d2m = W_(2, -1) - W_(-2, 1);
+    d.d12 = W_(1, 2) - W_(-1, -2);
+    d.d1m2 = W_(1, -2) - W_(-1, 2);
+    d.d22 = W_(2, 2) - W_(-2, -2);
+    d.d2m2 = W_(2, -2) - W_(-2, 2);
+#undef W_
     return d;
 }
 
@@ -505,88 +521,128 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
 }
 
 // ------------------------------------------------------------------------------------------
-// k_thermal: Runge-Kutta update of the temperature equation (eq. energy) on an LDS tile
+// k_thermal: Runge-Kutta update of the temperature equation (eq. energy) for one tile
 // ------------------------------------------------------------------------------------------
-enum : unsigned char { F_SOLID = 1, F_INLET = 2, F_OUTLET = 4 };
+// The frozen fields rho, u and T^n are loaded with a halo of 2 nodes per stage, so the stages
+// never leave the CU: stage s updates the tile grown by 2 (NS - s) nodes.  Each thread owns a
+// fixed set of positions ("slots") for the whole kernel and keeps their stage-invariant
+// coefficients, T^n and the Runge-Kutta accumulator in registers; only the stage input Y (and
+// rho, u for the invariants) live in LDS.  Slots are numbered ring by ring outwards from the
+// tile, so the positions of a later, smaller stage are a prefix of the numbering and whole
+// wavefronts drop out as the stages shrink.
+template <int TX, int TY, int NS> struct ThGeom {
+    static constexpr int H = 2 * NS;
+    static constexpr int RW = TX + 2 * H, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
+    static constexpr int count(int s) { return (TX + 4 * (NS - s)) * (TY + 4 * (NS - s)); }
+    static constexpr int NSLOT = count(1);
+};
+
+template <int TX, int TY, int NS> struct SlotTable {
+    unsigned short pos[ThGeom<TX, TY, NS>::NSLOT];
+};
+
+template <int TX, int TY, int NS> constexpr SlotTable<TX, TY, NS> make_slots()
+{
+    using G = ThGeom<TX, TY, NS>;
+    SlotTable<TX, TY, NS> t{};
+    int r = 0;
+    for (int y = 0; y < TY; ++y)
+        for (int x = 0; x < TX; ++x) t.pos[r++] = (unsigned short)((G::H + y) * G::RW + G::H + x);
+    // ring k: the tile grown by 2k nodes minus the tile grown by 2(k - 1)
+    for (int k = 1; k < NS; ++k) {
+        const int o = G::H - 2 * k, A = TX + 4 * (k - 1), B = TY + 4 * (k - 1);
+        for (int yy = 0; yy < 2; ++yy)
+            for (int xx = 0; xx < A + 4; ++xx) t.pos[r++] = (unsigned short)((o + yy) * G::RW + o + xx);
+        for (int yy = 0; yy < 2; ++yy)
+            for (int xx = 0; xx < A + 4; ++xx) t.pos[r++] = (unsigned short)((o + B + 2 + yy) * G::RW + o + xx);
+        for (int yy = 0; yy < B; ++yy)
+            for (int q = 0; q < 4; ++q) t.pos[r++] = (unsigned short)((o + 2 + yy) * G::RW + o + (q < 2 ? q : A + q));
+    }
+    return t;
+}
+
+template <int TX, int TY, int NS> __constant__ const SlotTable<TX, TY, NS> kSlots = make_slots<TX, TY, NS>();
 
 template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
-    static constexpr int H = 2 * NS;  // frozen-field halo: 2 nodes per stage
-    static constexpr int RW = TX + 2 * H, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
+    using G = ThGeom<TX, TY, NS>;
+    static constexpr int H = G::H, RW = G::RW, RN = G::RN, TN = G::TN, NSLOT = G::NSLOT;
+    static constexpr int ITER = (NSLOT + NT - 1) / NT;
 
     struct Smem {
-        C ux[RN], uy[RN], T0[RN], Y[RN];  // Y holds rho until the invariants exist
-        C gx[RN], gy[RN], c1[RN], c2[RN];
-        C acc[TN];
-        unsigned char flag[RN];
+        C Y[RN], rho[RN], ux[RN], uy[RN];
+    };
+    // per-slot state, in registers
+    struct Slots {
+        int own[ITER];  // LDS position of the slot
+        int ev[ITER];   // LDS position the operator is evaluated at; < 0: value held (solid, inlet ghost)
+        C T0[ITER], acc[ITER], u[ITER], v[ITER], au[ITER], av[ITER], gx[ITER], gy[ITER], c1[ITER], c2[ITER];
     };
 
-    // stage s of the Runge-Kutta update on the tile grown by 2 (NS - s) nodes
-    template <int s>
-    __device__ static void stage(Smem &sm, const Consts<C> &K, C cd, int out_c)
+    // right-hand side L(Y) of eq. energy at LDS position c with the coefficients of slot j
+    __device__ static C rhs(const Smem &sm, const Consts<C> &K, const Slots &S, int j, int c)
     {
-        constexpr int m = 2 * (NS - s);
-        constexpr int W = TX + 2 * m, N = W * (TY + 2 * m);
-        constexpr int ITER = (N + NT - 1) / NT;
+        // the 5x5 window read as positive offsets from its lowest corner
+        const C *b = sm.Y + opaque_index(c - 2 * RW - 2);
+#define Y_(dx, dy) b[(2 + (dy)) * RW + 2 + (dx)]
+        const C y0 = Y_(0, 0);
+        // sums and differences of opposite neighbours
+        const C p10 = Y_(1, 0), m10 = Y_(-1, 0), p20 = Y_(2, 0), m20 = Y_(-2, 0);
+        const C p01 = Y_(0, 1), m01 = Y_(0, -1), p02 = Y_(0, 2), m02 = Y_(0, -2);
+        const C S10 = p10 + m10, S20 = p20 + m20, S01 = p01 + m01, S02 = p02 + m02;
+        PairD<C> d;
+        d.d10 = p10 - m10; d.d20 = p20 - m20; d.d01 = p01 - m01; d.d02 = p02 - m02;
+        const C a11 = Y_(1, 1), b11 = Y_(-1, -1), a1m = Y_(1, -1), b1m = Y_(-1, 1);
+        const C a21 = Y_(2, 1), b21 = Y_(-2, -1), a2m = Y_(2, -1), b2m = Y_(-2, 1);
+        const C a12 = Y_(1, 2), b12 = Y_(-1, -2), a1m2 = Y_(1, -2), b1m2 = Y_(-1, 2);
+        const C a22 = Y_(2, 2), b22 = Y_(-2, -2), a2m2 = Y_(2, -2), b2m2 = Y_(-2, 2);
+#undef Y_
+        d.d11 = a11 - b11; d.d1m = a1m - b1m; d.d21 = a21 - b21; d.d2m = a2m - b2m;
+        d.d12 = a12 - b12; d.d1m2 = a1m2 - b1m2; d.d22 = a22 - b22; d.d2m2 = a2m2 - b2m2;
+        // isotropic Laplacian 2 sum_k w_k (Y(x + e_k) - Y(x))
+        const C lap = (C)2 * ((C)W1 * (S10 + S01) + (C)W2 * ((a11 + b11) + (a1m + b1m)) + (C)W4 * (S20 + S02) +
+                              (C)W5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
+                              (C)W8 * ((a22 + b22) + (a2m2 + b2m2))) -
+                      (C)(2.0 * WSUM) * y0;
+        // third-order upwind-biased convection (au, av: |u| times the dissipation coefficient)
+        const C conv = S.u[j] * ((C)8 * d.d10 - d.d20) * (C)(1.0 / 12.0) + S.au[j] * (S20 - (C)4 * S10 + (C)6 * y0) +
+                       S.v[j] * ((C)8 * d.d01 - d.d02) * (C)(1.0 / 12.0) + S.av[j] * (S02 - (C)4 * S01 + (C)6 * y0);
+        const C diff = K.alpha * lap + S.gx[j] * d.gx() + S.gy[j] * d.gy();
+        // pressure-work source T (c1 + c2 phi'(T)) with phi'(T) = A / sqrt(T) + B
+        const C src = S.c1[j] * y0 + S.c2[j] * Ar<C>::sqrt_(y0);
+        return diff + src - conv;
+    }
+
+    // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input
+    template <int s>
+    __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S)
+    {
+        constexpr int CNT = G::count(s);
         C kv[ITER];
 #pragma unroll
         for (int j = 0; j < ITER; ++j) {
             kv[j] = 0;
             const int r = threadIdx.x + NT * j;
-            if (r >= N) continue;
-            const int lx = H - m + r % W, ly = H - m + r / W;
-            const unsigned char fl = sm.flag[ly * RW + lx];
-            if (fl & (F_SOLID | F_INLET)) continue;
-            // an outlet ghost evaluates the operator at the last column of its row
-            const int c = ly * RW + ((fl & F_OUTLET) ? out_c : lx);
-            const C *Y = sm.Y;
-            const C y0 = Y[c];
-            // sums and differences of opposite neighbours
-            const C p10 = Y[c + 1], m10 = Y[c - 1], p20 = Y[c + 2], m20 = Y[c - 2];
-            const C p01 = Y[c + RW], m01 = Y[c - RW], p02 = Y[c + 2 * RW], m02 = Y[c - 2 * RW];
-            const C S10 = p10 + m10, S20 = p20 + m20, S01 = p01 + m01, S02 = p02 + m02;
-            PairD<C> d;
-            d.d10 = p10 - m10; d.d20 = p20 - m20; d.d01 = p01 - m01; d.d02 = p02 - m02;
-            const C a11 = Y[c + RW + 1], b11 = Y[c - RW - 1], a1m = Y[c - RW + 1], b1m = Y[c + RW - 1];
-            const C a21 = Y[c + RW + 2], b21 = Y[c - RW - 2], a2m = Y[c - RW + 2], b2m = Y[c + RW - 2];
-            const C a12 = Y[c + 2 * RW + 1], b12 = Y[c - 2 * RW - 1], a1m2 = Y[c - 2 * RW + 1], b1m2 = Y[c + 2 * RW - 1];
-            const C a22 = Y[c + 2 * RW + 2], b22 = Y[c - 2 * RW - 2], a2m2 = Y[c - 2 * RW + 2], b2m2 = Y[c + 2 * RW - 2];
-            d.d11 = a11 - b11; d.d1m = a1m - b1m; d.d21 = a21 - b21; d.d2m = a2m - b2m;
-            d.d12 = a12 - b12; d.d1m2 = a1m2 - b1m2; d.d22 = a22 - b22; d.d2m2 = a2m2 - b2m2;
-            // isotropic Laplacian 2 sum_k w_k (Y(x + e_k) - Y(x))
-            const C lap = (C)2 * ((C)W1 * (S10 + S01) + (C)W2 * ((a11 + b11) + (a1m + b1m)) + (C)W4 * (S20 + S02) +
-                                  (C)W5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
-                                  (C)W8 * ((a22 + b22) + (a2m2 + b2m2))) -
-                          (C)(2.0 * WSUM) * y0;
-            // third-order upwind-biased convection
-            const C u = sm.ux[c], v = sm.uy[c];
-            const C conv = u * ((C)8 * d.d10 - d.d20) * (C)(1.0 / 12.0) + fabs(u) * cd * (S20 - (C)4 * S10 + (C)6 * y0) +
-                           v * ((C)8 * d.d01 - d.d02) * (C)(1.0 / 12.0) + fabs(v) * cd * (S02 - (C)4 * S01 + (C)6 * y0);
-            const C diff = K.alpha * lap + sm.gx[c] * d.gx() + sm.gy[c] * d.gy();
-            // pressure-work source T (c1 + c2 phi'(T)) with phi'(T) = A / sqrt(T) + B
-            const C src = sm.c1[c] * y0 + sm.c2[c] * Ar<C>::sqrt_(y0);
-            kv[j] = diff + src - conv;
+            if (r >= CNT || S.ev[j] < 0) continue;
+            kv[j] = rhs(sm, K, S, j, S.ev[j]);
         }
-        __syncthreads();  // every stage input has been read
+        if constexpr (s < NS) __syncthreads();  // every stage input has been read
 #pragma unroll
         for (int j = 0; j < ITER; ++j) {
             const int r = threadIdx.x + NT * j;
-            if (r >= N) continue;
-            const int lx = H - m + r % W, ly = H - m + r / W;
-            const int c = ly * RW + lx;
-            const bool in_tile = lx >= H && lx < H + TX && ly >= H && ly < H + TY;
-            const int q = (ly - H) * TX + (lx - H);
+            if (r >= CNT || S.ev[j] < 0) continue;
             const C k = kv[j];
+            const int o = S.own[j];
             if constexpr (NS == 4) {
-                if constexpr (s == 1) { if (in_tile) sm.acc[q] = k; sm.Y[c] = sm.T0[c] + (C)0.5 * k; }
-                else if constexpr (s == 2) { if (in_tile) sm.acc[q] += (C)2 * k; sm.Y[c] = sm.T0[c] + (C)0.5 * k; }
-                else if constexpr (s == 3) { if (in_tile) sm.acc[q] += (C)2 * k; sm.Y[c] = sm.T0[c] + k; }
-                else { if (in_tile) sm.acc[q] = sm.T0[c] + (sm.acc[q] + k) * (C)(1.0 / 6.0); }
+                if constexpr (s == 1) { S.acc[j] = k; sm.Y[o] = S.T0[j] + (C)0.5 * k; }
+                else if constexpr (s == 2) { S.acc[j] += (C)2 * k; sm.Y[o] = S.T0[j] + (C)0.5 * k; }
+                else if constexpr (s == 3) { S.acc[j] += (C)2 * k; sm.Y[o] = S.T0[j] + k; }
+                else { S.acc[j] = S.T0[j] + (S.acc[j] + k) * (C)(1.0 / 6.0); }
             } else {
-                if constexpr (s == 1) { if (in_tile) sm.acc[q] = k; sm.Y[c] = sm.T0[c] + k; }
-                else { if (in_tile) sm.acc[q] = sm.T0[c] + (C)0.5 * (sm.acc[q] + k); }
+                if constexpr (s == 1) { S.acc[j] = k; sm.Y[o] = S.T0[j] + k; }
+                else { S.acc[j] = S.T0[j] + (C)0.5 * (S.acc[j] + k); }
             }
         }
-        __syncthreads();
+        if constexpr (s < NS) __syncthreads();
     }
 };
 
@@ -595,17 +651,17 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
                                                 long long step)
 {
     using Th = Thermal<C, TX, TY, NS, NT>;
-    constexpr int H = Th::H, RW = Th::RW, RH = Th::RH, RN = Th::RN, TN = Th::TN;
+    constexpr int H = Th::H, RW = Th::RW, RN = Th::RN, TN = Th::TN, NSLOT = Th::NSLOT, ITER = Th::ITER;
     __shared__ typename Th::Smem sm;
 
     const Tile t = tiles[blockIdx.x];
     const RunDev &R = runs[t.run];
     const int x0 = t.tx * TX, y0 = t.ty * TY;
     const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const gp<const C> Tin = gin<C>(R.T[pt]);
-    const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
     if (step < R.warmup || R.rk == 0) {
         // this run does not advance its temperature in this step: carry T over
+        const gp<const C> Tin = gin<C>(R.T[pt]);
+        const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
         for (int q = threadIdx.x; q < TN; q += NT) {
             const int gx = x0 + q % TX, gy = y0 + q / TX;
             if (gx < nx && gy < ny) Tout[(size_t)gy * P + gx] = Tin[(size_t)gy * P + gx];
@@ -614,59 +670,77 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
     }
     const Consts<C> K(R);
 
-    // load the frozen fields and T^n on the whole region
+    // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
     for (int p = threadIdx.x; p < RN; p += NT) {
         const int lx = p % RW, ly = p / RW;
         int rx, ry;
         const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
         const unsigned idx = (unsigned)(ry * P + rx);
-        sm.Y[p] = ld_at<C>(R.rho, idx);
+        sm.rho[p] = ld_at<C>(R.rho, idx);
         sm.ux[p] = ld_at<C>(R.ux, idx);
         sm.uy[p] = ld_at<C>(R.uy, idx);
-        sm.T0[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
-        sm.flag[p] = (unsigned char)((solid_at(R, rx, ry) ? F_SOLID : 0) | (kind == INLET_GHOST ? F_INLET : 0) |
-                                     (kind == OUTLET_GHOST ? F_OUTLET : 0));
+        sm.Y[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
     }
     __syncthreads();
 
-    // stage-invariant coefficients on the region shrunk by 2:
+    // slots and their stage-invariant coefficients:
     //   gx, gy = alpha grad(rho)/rho;  source(T) = c1 T + c2 sqrt(T) with
     //   D = div(u)/(rho cv), c1 = -D R rho/(1 - b rho) + B D a rho^2/(1 + 2 b rho - b^2 rho^2),
     //   c2 = A D a rho^2/(1 + 2 b rho - b^2 rho^2), phi'(T) = A/sqrt(T) + B
-    for (int p = threadIdx.x; p < RN; p += NT) {
+    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
+    const int out_c = (nx - 1) - (x0 - H);  // LDS column of the last domain column
+    typename Th::Slots S;
+#pragma unroll
+    for (int j = 0; j < ITER; ++j) {
+        S.own[j] = 0; S.ev[j] = -1;
+        S.T0[j] = S.acc[j] = S.u[j] = S.v[j] = S.au[j] = S.av[j] = S.gx[j] = S.gy[j] = S.c1[j] = S.c2[j] = 0;
+        const int r = threadIdx.x + NT * j;
+        if (r >= NSLOT) continue;
+        const int p = kSlots<TX, TY, NS>.pos[r];
         const int lx = p % RW, ly = p / RW;
-        if (lx < 2 || lx >= RW - 2 || ly < 2 || ly >= RH - 2) continue;
-        const PairD<C> dr = pair_diffs<RW>(sm.Y, p);
-        const PairD<C> du = pair_diffs<RW>(sm.ux, p);
-        const PairD<C> dv = pair_diffs<RW>(sm.uy, p);
-        const C rho = sm.Y[p];
+        int rx, ry;
+        const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        S.own[j] = p;
+        S.T0[j] = sm.Y[p];
+        if (kind == INLET_GHOST || solid_at(R, rx, ry)) continue;
+        // an outlet ghost evaluates the operator at the last column of its row
+        const int c = kind == OUTLET_GHOST ? ly * RW + out_c : p;
+        S.ev[j] = c;
+        const PairD<C> dr = pair_diffs<RW>(sm.rho, c);
+        const PairD<C> du = pair_diffs<RW>(sm.ux, c);
+        const PairD<C> dv = pair_diffs<RW>(sm.uy, c);
+        const C rho = sm.rho[c];
         const C ir = Ar<C>::rcp(rho);
-        sm.gx[p] = K.alpha * dr.gx() * ir;
-        sm.gy[p] = K.alpha * dr.gy() * ir;
+        S.gx[j] = K.alpha * dr.gx() * ir;
+        S.gy[j] = K.alpha * dr.gy() * ir;
         const C D = (du.gx() + dv.gy()) * ir * K.inv_cv;
         const C d1 = (C)1 - K.b * rho;
         const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
         const C A2 = D * K.a * rho * rho * Ar<C>::rcp(d2);
-        sm.c1[p] = -D * rho * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
-        sm.c2[p] = K.dphi_A * A2;
+        S.c1[j] = -D * rho * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
+        S.c2[j] = K.dphi_A * A2;
+        const C u = sm.ux[c], v = sm.uy[c];
+        S.u[j] = u;
+        S.v[j] = v;
+        S.au[j] = fabs(u) * cd;
+        S.av[j] = fabs(v) * cd;
     }
-    __syncthreads();
-    for (int p = threadIdx.x; p < RN; p += NT) sm.Y[p] = sm.T0[p];
-    __syncthreads();
 
-    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
-    const int out_c = (nx - 1) - (x0 - H);  // LDS column of the last domain column
-    Th::template stage<1>(sm, K, cd, out_c);
-    Th::template stage<2>(sm, K, cd, out_c);
+    Th::template stage<1>(sm, K, S);
+    Th::template stage<2>(sm, K, S);
     if constexpr (NS == 4) {
-        Th::template stage<3>(sm, K, cd, out_c);
-        Th::template stage<4>(sm, K, cd, out_c);
+        Th::template stage<3>(sm, K, S);
+        Th::template stage<4>(sm, K, S);
     }
 
-    for (int q = threadIdx.x; q < TN; q += NT) {
-        const int gx = x0 + q % TX, gy = y0 + q / TX;
+    // the tile's slots come first
+#pragma unroll
+    for (int j = 0; j < ITER; ++j) {
+        const int r = threadIdx.x + NT * j;
+        if (NT * j >= TN || r >= TN) continue;
+        const int gx = x0 + r % TX, gy = y0 + r / TX;
         if (gx >= nx || gy >= ny) continue;
-        *at<C>(R.T[pt ^ 1], (unsigned)(gy * P + gx)) = solid_at(R, gx, gy) ? K.T_w : sm.acc[q];
+        *at<C>(R.T[pt ^ 1], (unsigned)(gy * P + gx)) = S.ev[j] < 0 ? K.T_w : S.acc[j];
     }
 }
 
@@ -784,14 +858,14 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // stream+collide: FP32 and reduced-precision storage / FP64
 static const Variant kLbm32[] = {{32, 16, 256}, {64, 16, 512}, {32, 32, 512}, {32, 8, 256}};
 static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
-// temperature update (LDS holds 8 fields of the tile grown by 2 nodes per stage)
-static const Variant kTh32[] = {{32, 32, 512}, {32, 16, 256}, {64, 32, 512}, {16, 16, 256}};
+// temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
+static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}, {64, 64, 1024}};
 static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
 
 int variant_count(int precision, int kernel)
 {
     if (kernel == 0) return precision == 0 ? 2 : 4;
-    return precision == 0 ? 2 : 4;
+    return precision == 0 ? 2 : 5;
 }
 
 Variant variant_shape(int precision, int kernel, int v)
@@ -865,10 +939,11 @@ hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs
         }
     }
     switch (variant) {
-    case 0: return th_go<float, 32, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 1: return th_go<float, 32, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 2: return th_go<float, 64, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 3: return th_go<float, 16, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 0: return th_go<float, 64, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 1: return th_go<float, 32, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 2: return th_go<float, 64, 32, 1024>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 3: return th_go<float, 32, 32, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 4: return th_go<float, 64, 64, 1024>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
     default: return hipErrorInvalidValue;
     }
 }
