@@ -183,6 +183,9 @@ struct Layout {
     int n_lbm, n_th;
 };
 
+// entries of the cut-link table: 8 directions per node of the box |x - x_c|, |y - y_c| <= R + 1
+size_t qtab_count(int cyl_r) { return cyl_r > 0 ? (size_t)(2 * cyl_r + 3) * (2 * cyl_r + 3) * 8 : 0; }
+
 size_t run_bytes(const lbm_config &k)
 {
     const size_t plane = (size_t)k.ny * pitch_of(k.nx);
@@ -194,6 +197,7 @@ size_t run_bytes(const lbm_config &k)
     b += align256(2 * sizeof(double) * std::max(1, probe_count(k.cyl_r)));  // probes
     b += align256(sizeof(double) * lbm::kDiagBlocks);       // partials
     b += align256(sizeof(double) * 8);                      // acc
+    b += align256(qtab_count(k.cyl_r) * cb);                // wall fractions of cut links
     return b;
 }
 
@@ -261,6 +265,38 @@ bool solid_host(const RunDev &R, int x, int y)
     if (R.cyl_r <= 0) return false;
     long dx = x - R.cyl_x, dy = y - R.cyl_y;
     return dx * dx + dy * dy <= (long)R.cyl_r * R.cyl_r;
+}
+
+// Wall fraction of the link from fluid node (x, y) along -c_i into the cylinder: the smaller root
+// q of |d - q c_i|^2 = R^2 with d the node's offset from the centre (linear interpolated
+// bounce-back, Sec. IV A).  Tabulated in the compute type with its branch folded in (see fix_near
+// in the kernels): 0 = plain pull, 2q in (0,1) or 4 for q < 1/2 (with / without a fluid node at
+// x + c_i), -2q for q >= 1/2.
+std::vector<unsigned char> cut_link_table(const RunDev &R, int prec)
+{
+    const size_t n = qtab_count(R.cyl_r);
+    std::vector<unsigned char> out(n * compute_bytes(prec), 0);
+    if (!n) return out;
+    static const int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1}, cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    const int bw = 2 * R.cyl_r + 3, bx0 = R.cyl_x - R.cyl_r - 1, by0 = R.cyl_y - R.cyl_r - 1;
+    for (int by = 0; by < bw; ++by)
+        for (int bx = 0; bx < bw; ++bx) {
+            const int x = bx0 + bx, y = by0 + by;
+            if (solid_host(R, x, y)) continue;
+            for (int i = 1; i < 9; ++i) {
+                if (!solid_host(R, x - cx[i], y - cy[i])) continue;
+                const double dx = x - R.cyl_x, dy = y - R.cyl_y;
+                const double c2 = cx[i] * cx[i] + cy[i] * cy[i], dc = dx * cx[i] + dy * cy[i];
+                const double Rr = R.cyl_r;
+                const double disc = dc * dc - c2 * (dx * dx + dy * dy - Rr * Rr);
+                const double q = (dc - std::sqrt(disc)) / c2;
+                double v;
+                if (q < 0.5) v = solid_host(R, x + cx[i], y + cy[i]) ? 4.0 : 2.0 * q;
+                else v = -(2.0 * q);
+                st_compute(out.data(), prec, (size_t)(by * bw + bx) * 8 + (i - 1), v);
+            }
+        }
+    return out;
 }
 
 // Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD b mod 8), each XCD
@@ -447,6 +483,7 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         R.probes = (const double *)p; p += align256(2 * sizeof(double) * std::max(1, R.np));
         R.partials = (double *)p; p += align256(sizeof(double) * lbm::kDiagBlocks);
         R.acc = (double *)p; p += align256(sizeof(double) * 8);
+        R.qtab = qtab_count(R.cyl_r) ? p : nullptr; p += align256(qtab_count(R.cyl_r) * cb);
         h->runs.push_back(R);
 
         // probe ring at radius R + 1.5
@@ -467,7 +504,14 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         delete h;
         return rc;
     }
+    std::vector<std::vector<unsigned char>> qtabs(n_runs);
     for (int r = 0; r < n_runs; ++r) {
+        qtabs[r] = cut_link_table(h->runs[r], prec);
+        if (!qtabs[r].empty() && (rc = upload((void *)h->runs[r].qtab, qtabs[r].data(), qtabs[r].size()))) {
+            g_create_error = h->err;
+            delete h;
+            return rc;
+        }
         if ((rc = upload((void *)h->runs[r].probes, probes[r].data(), sizeof(double) * probes[r].size()))) {
             g_create_error = h->err;
             delete h;

@@ -32,6 +32,7 @@ struct RunDev {
     void *rho, *ux, *uy;      // macroscopic fields of the last streamed state, compute type
     void *hist[2];            // outlet history, compute type, [3][ny]
     const double *probes;     // [np][2] probe coordinates
+    const void *qtab;         // compute type, [2R+3][2R+3][8] wall fractions of cut links (cyl_r > 0)
     double *partials;         // [kDiagBlocks] partial mass sums
     double *acc;              // [8]: mass, q_mean, nu, nu_sum, nu_count, nonfinite
 };

@@ -175,19 +175,10 @@ __device__ inline C ldf(const char *base, unsigned plane, unsigned pitch, int i,
     return Conv<S>::ld(*(gp<const RawT<S>>)(base + off), K.shiftw[i]);
 }
 
-__device__ inline double link_q(const RunDev &R, int x, int y, int i)
-{
-    // smaller root of |d - q c|^2 = R^2, d = node - centre (exact integers up to the sqrt)
-    const double dx = x - R.cyl_x, dy = y - R.cyl_y, cx = cx_of(i), cy = cy_of(i);
-    const double c2 = cx * cx + cy * cy, dc = dx * cx + dy * cy;
-    const double Rr = R.cyl_r;
-    const double disc = dc * dc - c2 * (dx * dx + dy * dy - Rr * Rr);
-    return (dc - sqrt(disc)) / c2;
-}
-
 // Plain pulls of a node away from the cylinder; at the inlet / outlet columns the sources outside
-// the domain are clamped in (their values are replaced by apply_x_bc).  Offsets are formed once per
-// node: one row product, neighbouring rows and columns by adds and selects.
+// the domain are clamped in (apply_x_bc then replaces the inlet's unknowns; at the outlet the clamped
+// values are the ones the convective condition needs).  Offsets are formed once per node: one row
+// product, neighbouring rows and columns by adds and selects.
 template <typename S, typename C>
 __device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
@@ -209,63 +200,58 @@ __device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char
     }
 }
 
+// A fluid node with a link into the cylinder lies within R + sqrt(2) of the centre; the test
+// (R + 1)(R + 2) bounds that and keeps |x - x_c|, |y - y_c| <= R + 1 (the cut-link table's box).
 __device__ inline bool near_cylinder(const RunDev &R, int x, int y)
 {
-    return R.cyl_r > 0 && abs(x - R.cyl_x) <= R.cyl_r + 1 && abs(y - R.cyl_y) <= R.cyl_r + 1;
+    const int dx = x - R.cyl_x, dy = y - R.cyl_y;
+    return R.cyl_r > 0 && dx * dx + dy * dy <= (R.cyl_r + 1) * (R.cyl_r + 2);
 }
 
-// Pulls of a node next to the cylinder: links whose source is solid use the linear interpolated
-// bounce-back on the curved wall.
+// Links of a node next to the cylinder whose source is solid: linear interpolated bounce-back on
+// the curved wall.  The wall fraction of every cut link is tabulated on the host over the box
+// |x - x_c|, |y - y_c| <= R + 1 (8 entries per node, directions 1..8):
+//   0          the source is fluid: the plain pull stands
+//   v in (0,1) q < 1/2 with a fluid node at x + c_i:  f_i = v f*_o(x) + (1 - v) f*_o(x + c_i), v = 2q
+//   v > 2      q < 1/2 without one:                    f_i = f*_o(x)
+//   v <= -1    q >= 1/2:                              f_i = f*_o(x)/(2q) + (2q - 1)/(2q) f*_i(x), v = -2q
+// The box keeps one node clear of every domain edge, so no neighbour index wraps.
 template <typename S, typename C>
-__device__ void pull_near(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
+__device__ inline void fix_near(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
-    const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const unsigned plane = (unsigned)ny * P;
-    const bool periodic = R.bc_x == 0;
+    const unsigned P = R.pitch, plane = (unsigned)R.ny * P;
+    const int bw = 2 * R.cyl_r + 3;
+    const C *qt = (const C *)R.qtab + ((y - (R.cyl_y - R.cyl_r - 1)) * bw + (x - (R.cyl_x - R.cyl_r - 1))) * 8;
+    // every operand is loaded up front (one round trip), then each link selects its rule
+    C v[9], own[9], nb[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int xs = x - cx_of(i), ys = wrap(y - cy_of(i), ny);
-        if (!solid_at(R, xs, ys)) {
-            f[i] = ldf<S, C>(fin, plane, P, i, xs, ys, K);
-            continue;
-        }
-        const int o = opp_of(i);
-        const double q = link_q(R, x, y, i);
-        const C fo = ldf<S, C>(fin, plane, P, o, x, y, K);
-        if (q < 0.5) {
-            int xn = x + cx_of(i);
-            const int yn = wrap(y + cy_of(i), ny);
-            if (periodic) xn = wrap(xn, nx);
-            const bool fluid_n = xn >= 0 && xn < nx && !solid_at(R, xn, yn);
-            if (fluid_n) {
-                const C q2 = (C)(2.0 * q);
-                f[i] = q2 * fo + ((C)1 - q2) * ldf<S, C>(fin, plane, P, o, xn, yn, K);
-            } else {
-                f[i] = fo;
-            }
-        } else {
-            const C q2 = (C)(2.0 * q);
-            f[i] = fo / q2 + (q2 - (C)1) / q2 * ldf<S, C>(fin, plane, P, i, x, y, K);
-        }
+    for (int i = 1; i < 9; ++i) {
+        v[i] = qt[i - 1];
+        own[i] = ldf<S, C>(fin, plane, P, i, x, y, K);
+        nb[i] = ldf<S, C>(fin, plane, P, opp_of(i), x + cx_of(i), y + cy_of(i), K);
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const C fo = own[opp_of(i)];
+        const C q2 = -v[i];
+        const C lt = v[i] * fo + ((C)1 - v[i]) * nb[i];
+        const C ge = fo / q2 + (q2 - (C)1) / q2 * own[i];
+        f[i] = v[i] == (C)0 ? f[i] : (v[i] > (C)2 ? fo : (v[i] > (C)0 ? lt : ge));
     }
 }
 
 // Velocity inlet at x = 0 and convective outlet at x = nx - 1.
 template <typename S, typename C>
-__device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, const char *fin, gp<const C> hin, int x,
-                                  int y, C f[9])
+__device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, gp<const C> hin, int x, int y, C f[9])
 {
-    const int nx = R.nx, ny = R.ny, P = R.pitch;
-    const unsigned plane = (unsigned)ny * P;
+    const int nx = R.nx, ny = R.ny;
     if (x == nx - 1) {
-        // convective outflow: f^{n+1}(N) = (f^n(N) + U f^{n+1}(N-1)) / (1 + U), i in {2,6,8}
-        const int ym = y == 0 ? ny - 1 : y - 1;
-        const int yp = y == ny - 1 ? 0 : y + 1;
+        // convective outflow: f^{n+1}(N) = (f^n(N) + U f^{n+1}(N-1)) / (1 + U), i in {2,6,8}.  The
+        // plain pulls of column N clamp their x source to N, so f[2], f[6], f[8] already hold
+        // f*_2(N, y), f*_6(N, y + 1), f*_8(N, y - 1): the populations that stream into N - 1.
         const C U = K.u_in;
         const C inv = Ar<C>::rcp((C)1 + U);
-        const C p2 = ldf<S, C>(fin, plane, P, 2, nx - 1, y, K);
-        const C p6 = ldf<S, C>(fin, plane, P, 6, nx - 1, yp, K);
-        const C p8 = ldf<S, C>(fin, plane, P, 8, nx - 1, ym, K);
+        const C p2 = f[2], p6 = f[6], p8 = f[8];
         f[2] = (hin[0 * ny + y] + U * p2) * inv;
         f[6] = (hin[1 * ny + y] + U * p6) * inv;
         f[8] = (hin[2 * ny + y] + U * p8) * inv;
@@ -280,21 +266,13 @@ __device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, const cha
     }
 }
 
-template <typename C> struct F9 {
-    C v[9];
-};
-
-// Streaming of a node next to the cylinder or on an inlet / outlet column (rare; kept out of line
-// so the unrolled bulk path stays small).
+// Corrections of the plain pulls f of a node next to the cylinder or on an inlet / outlet column.
 template <typename S, typename C>
-__device__ __attribute__((noinline)) F9<C> pull_special(const RunDev &R, const char *fin, const void *hin, int x, int y)
+__device__ inline void fix_special(const RunDev &R, const Consts<C> &K, const char *fin, const void *hin, int x, int y,
+                                   C f[9])
 {
-    const Consts<C> K(R);
-    F9<C> r;
-    if (near_cylinder(R, x, y)) pull_near<S, C>(R, K, fin, x, y, r.v);
-    else pull_bulk<S, C>(R, K, fin, x, y, r.v);
-    if (R.bc_x == 1 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, fin, gin<C>(hin), x, y, r.v);
-    return r;
+    if (near_cylinder(R, x, y)) fix_near<S, C>(R, K, fin, x, y, f);
+    if (R.bc_x == 1 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, gin<C>(hin), x, y, f);
 }
 
 // An index the optimiser cannot re-associate with the constant offsets added to it afterwards,
@@ -365,8 +343,6 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
     const bool fon = step >= R.warmup;
     const char *fin = (const char *)R.f[pf];
     char *fout = (char *)R.f[pf ^ 1];
-    const gp<const C> Tc = gin<C>(R.T[pt]);
-    const gp<const C> hin = gin<C>(R.hist[ph]);
     const gp<C> hout = gout<C>(R.hist[ph ^ 1]);
 
     // phase 1: density (and psi) on the tile plus halo, raw moments on the tile.  Each thread
@@ -414,11 +390,8 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
             if (own) { s_m[0][q] = rho; s_m[1][q] = 0; s_m[2][q] = 0; s_m[3][q] = 0; s_m[4][q] = 0; }
         } else {
             C *f = fv[j];
-            if (near_cylinder(R, rx, ry) || (R.bc_x == 1 && (rx == 0 || rx == nx - 1))) {
-                const F9<C> sp = pull_special<S, C>(R, fin, R.hist[ph], rx, ry);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) f[i] = sp.v[i];
-            }
+            if (near_cylinder(R, rx, ry) || (R.bc_x == 1 && (rx == 0 || rx == nx - 1)))
+                fix_special<S, C>(R, K, fin, R.hist[ph], rx, ry, f);
             rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
             T = ((inlet >> j) & 1u) ? K.T_sat : Tv[j];
             if (own) {
