@@ -50,8 +50,11 @@ enum {
 };
 
 /* arithmetic of the step: FP64; FP32; FP32 compute with populations stored as FP16 or BF16
- * holding f_i - w_i * rho_ref_shift (temperature and macroscopic fields stay FP32) */
-enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_BF16S = 3 };
+ * holding f_i - w_i * rho_ref_shift (temperature and macroscopic fields stay FP32);
+ * LBM_F64_TANGENT: the FP64 step in forward-mode dual numbers, every value carrying its
+ * derivatives along LBM_TANGENTS parameter directions (see lbm_nu_tangent) */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_BF16S = 3, LBM_F64_TANGENT = 4 };
+enum { LBM_TANGENTS = 4 };
 
 /* x boundaries; y is always periodic */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_INLET_OUTLET = 1 };
@@ -78,7 +81,7 @@ typedef struct {
     double u_in;            /* inlet velocity (also the outlet convection speed) */
     double alpha_T;         /* thermal diffusivity */
     double cv;              /* specific heat at constant volume */
-    int32_t precision;      /* LBM_FP64 ... LBM_BF16S; all runs of a handle share it */
+    int32_t precision;      /* LBM_FP64 ... LBM_F64_TANGENT; all runs of a handle share it */
     int32_t check_every;    /* > 0: lbm_step checks the state for non-finite values */
     double rho_ref_shift;   /* reduced-precision storage offset rho_ref (f_i - w_i rho_ref) */
 } lbm_config;
@@ -123,6 +126,25 @@ int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *his
  * mean, nu = q_mean 2R / (rho_v c_v alpha dT); nu_time_avg is the mean of the Nu values
  * accumulated during lbm_step (0 if none).  FP64.  Waits for the stream. */
 int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, double *nu_time_avg);
+
+/* Sensitivities of the wall Nusselt number (tangent precision only; LBM_EINVAL otherwise).
+ * The tangent directions are the parameters, in this order:
+ *   0  dTr_wall  (wall superheat / T_c; T_w = T_sat + dTr_wall T_c)
+ *   1  u_in      (inlet velocity, also the outlet convection speed)
+ *   2  acentric  (Peng-Robinson acentric factor, through kappa, eq. eos)
+ *   3  tau       (relaxation time 3 nu + 1/2, with alpha_T scaled alongside so that nu/alpha_T
+ *                 is held)
+ * with the coexistence densities rho_l, rho_v (and every density derived from them), T_sat, c_v
+ * and the geometry held fixed.  dnu[k] = d Nu / d theta_k of the current state; dnu_time_avg[k]
+ * = d/d theta_k of the time average reported by lbm_wall_heat_flux.  The default state of
+ * lbm_create carries d u / d u_in = 1; states set by lbm_set_fields / lbm_set_state carry zero
+ * derivatives.  Derivatives are exact for the discrete step (forward mode) up to FP64 rounding.
+ * Either pointer may be NULL (4 doubles each).  Waits for the stream. */
+int lbm_nu_tangent(lbm_handle *h, int run, double *dnu, double *dnu_time_avg);
+
+/* Restart the time average of Nu (and of its tangents) of one run: the next lbm_step
+ * accumulations start a new window.  Waits for the stream. */
+int lbm_reset_time_average(lbm_handle *h, int run);
 
 /* FP64 sum of rho over the fluid nodes of the current state.  Waits for the stream. */
 int lbm_total_mass(lbm_handle *h, int run, double *mass);

@@ -15,8 +15,11 @@ import dataclasses
 import math
 from dataclasses import dataclass, field
 
-FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
-PRECISION_NAMES = {FP64: "f64", FP32: "f32", FP16S: "f16-store", BF16S: "bf16-store"}
+FP64, FP32, FP16S, BF16S, F64_TANGENT = 0, 1, 2, 3, 4
+PRECISION_NAMES = {FP64: "f64", FP32: "f32", FP16S: "f16-store", BF16S: "bf16-store",
+                   F64_TANGENT: "f64+tangents"}
+# parameter directions of the tangent precision (order of lbm_nu_tangent)
+TANGENT_PARAMS = ("dTr_wall", "u_in", "acentric", "tau")
 BC_PERIODIC, BC_INLET_OUTLET = 0, 1
 
 

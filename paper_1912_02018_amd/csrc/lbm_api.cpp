@@ -71,8 +71,14 @@ int fail(lbm_handle *h, int code, const char *fmt, ...)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
-size_t storage_bytes(int precision) { return precision == 0 ? 8 : (precision == 1 ? 4 : 2); }
-size_t compute_bytes(int precision) { return precision == 0 ? 8 : 4; }
+// bytes per stored population / per compute-type value; the tangent precision stores an FP64
+// value followed by its kTangents derivatives
+constexpr size_t kDualBytes = 8 * (1 + lbm::kTangents);
+size_t storage_bytes(int precision)
+{
+    return precision == 4 ? kDualBytes : (precision == 0 ? 8 : (precision == 1 ? 4 : 2));
+}
+size_t compute_bytes(int precision) { return precision == 4 ? kDualBytes : (precision == 0 ? 8 : 4); }
 int probe_count(int r) { return r > 0 ? 8 * (int)std::ceil(M_PI * r / 4.0) : 0; }
 
 // ---- Peng-Robinson thermodynamics on the host (set-up only) -----------------------------------
@@ -157,7 +163,9 @@ int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
         if (9.0 * k.ny * pitch_of(k.nx) * storage_bytes(k.precision) >= 4294967296.0)
             return fail(h, LBM_EINVAL, "run %d: grid too large (9 population planes must stay below 4 GiB)", r);
         if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET) return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
-        if (k.precision < 0 || k.precision > 3) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
+        if (k.precision < 0 || k.precision > 4) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
+        if (k.precision == 4 && probe_count(k.cyl_r) > lbm::kMaxTangentProbes)
+            return fail(h, LBM_EINVAL, "run %d: cylinder too large for the tangent precision", r);
         if (k.precision != c[0].precision) return fail(h, LBM_EINVAL, "all runs must share one precision");
         if (k.rk_stages != 0 && k.rk_stages != 2 && k.rk_stages != 4) return fail(h, LBM_EINVAL, "run %d: rk_stages must be 0, 2 or 4", r);
         if (k.rk_stages != c[0].rk_stages) return fail(h, LBM_EINVAL, "all runs must share rk_stages");
@@ -196,7 +204,7 @@ size_t run_bytes(const lbm_config &k)
     b += 2 * align256(3 * (size_t)k.ny * cb);               // hist[2]
     b += align256(2 * sizeof(double) * std::max(1, probe_count(k.cyl_r)));  // probes
     b += align256(sizeof(double) * lbm::kDiagBlocks);       // partials
-    b += align256(sizeof(double) * 8);                      // acc
+    b += align256(sizeof(double) * lbm::kAcc);              // acc
     b += align256(qtab_count(k.cyl_r) * cb);                // wall fractions of cut links
     return b;
 }
@@ -230,6 +238,7 @@ Layout layout(const lbm_config *c, int n)
 double ld_storage(const unsigned char *p, int prec, size_t k)
 {
     switch (prec) {
+    case 4: return ((const double *)p)[k * (1 + lbm::kTangents)];
     case 0: return ((const double *)p)[k];
     case 1: return ((const float *)p)[k];
     case 2: return (double)__half2float(((const __half *)p)[k]);
@@ -240,6 +249,10 @@ double ld_storage(const unsigned char *p, int prec, size_t k)
 void st_storage(unsigned char *p, int prec, size_t k, double v)
 {
     switch (prec) {
+    case 4:
+        ((double *)p)[k * (1 + lbm::kTangents)] = v;
+        for (int d = 1; d <= lbm::kTangents; ++d) ((double *)p)[k * (1 + lbm::kTangents) + d] = 0.0;
+        break;
     case 0: ((double *)p)[k] = v; break;
     case 1: ((float *)p)[k] = (float)v; break;
     case 2: ((__half *)p)[k] = __float2half_rn((float)v); break;
@@ -249,13 +262,22 @@ void st_storage(unsigned char *p, int prec, size_t k, double v)
 
 double ld_compute(const unsigned char *p, int prec, size_t k)
 {
+    if (prec == 4) return ((const double *)p)[k * (1 + lbm::kTangents)];
     return prec == 0 ? ((const double *)p)[k] : (double)((const float *)p)[k];
 }
 
-void st_compute(unsigned char *p, int prec, size_t k, double v)
+// store v (tangent precision: with zero derivatives, or derivative 1 along direction seed_dir)
+void st_compute(unsigned char *p, int prec, size_t k, double v, int seed_dir = -1)
 {
-    if (prec == 0) ((double *)p)[k] = v;
-    else ((float *)p)[k] = (float)v;
+    if (prec == 4) {
+        double *e = (double *)p + k * (1 + lbm::kTangents);
+        e[0] = v;
+        for (int d = 0; d < lbm::kTangents; ++d) e[1 + d] = d == seed_dir ? 1.0 : 0.0;
+    } else if (prec == 0) {
+        ((double *)p)[k] = v;
+    } else {
+        ((float *)p)[k] = (float)v;
+    }
 }
 
 const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -367,14 +389,16 @@ int check_run(lbm_handle *h, int run)
     return LBM_OK;
 }
 
-// upload host fields (double, [ny][nx]) into a pitched compute-type plane
-int upload_plane(lbm_handle *h, const RunDev &R, void *dst, const double *src, double fill)
+// upload host fields (double, [ny][nx]) into a pitched compute-type plane; seed_dir >= 0 gives
+// the values derivative 1 along that tangent direction
+int upload_plane(lbm_handle *h, const RunDev &R, void *dst, const double *src, double fill, int seed_dir = -1)
 {
     const size_t cb = compute_bytes(h->precision);
     std::vector<unsigned char> buf((size_t)R.ny * R.pitch * cb, 0);
     for (int y = 0; y < R.ny; ++y)
         for (int x = 0; x < R.nx; ++x)
-            st_compute(buf.data(), h->precision, (size_t)y * R.pitch + x, src ? src[(size_t)y * R.nx + x] : fill);
+            st_compute(buf.data(), h->precision, (size_t)y * R.pitch + x, src ? src[(size_t)y * R.nx + x] : fill,
+                       seed_dir);
     HIPCHK(h, hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -410,6 +434,9 @@ size_t lbm_workspace_bytes(const lbm_config *cfgs, int n_runs)
     if (validate(cfgs, n_runs, &prec, &rk, nullptr) != LBM_OK) return 0;
     return layout(cfgs, n_runs).total;
 }
+
+static int set_fields_impl(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy,
+                           const double *T, int ux_seed_dir);
 
 int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                lbm_handle **out)
@@ -470,6 +497,19 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         R.dphi_A = -R.kappa * (1.0 + R.kappa) / std::sqrt(R.Tc);
         R.dphi_B = R.kappa * R.kappa / R.Tc;
         R.inv_cv = 1.0 / R.cv;
+        if (prec == 4) {
+            // tangent directions: 0 superheat dTr_wall, 1 u_in, 2 acentric factor, 3 tau (at fixed
+            // nu/alpha ratio); the coexistence densities, T_sat and the other constants are held
+            const double tau = k.nu / (1.0 / 3.0) + 0.5;
+            const double dkappa = 1.54226 - 2.0 * 0.26992 * k.acentric;
+            R.t_T_w[0] = pr.Tc;
+            R.t_u_in[1] = 1.0;
+            R.t_kappa[2] = dkappa;
+            R.t_dphi_A[2] = -(1.0 + 2.0 * R.kappa) / std::sqrt(R.Tc) * dkappa;
+            R.t_dphi_B[2] = 2.0 * R.kappa / R.Tc * dkappa;
+            R.t_omega[3] = -1.0 / (tau * tau);
+            R.t_alpha[3] = R.alpha / (tau - 0.5);
+        }
 
         unsigned char *p = ws + L.run_off[r];
         const size_t plane = (size_t)R.ny * R.pitch;
@@ -482,7 +522,7 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         for (int b = 0; b < 2; ++b) { R.hist[b] = p; p += align256(3 * (size_t)R.ny * cb); }
         R.probes = (const double *)p; p += align256(2 * sizeof(double) * std::max(1, R.np));
         R.partials = (double *)p; p += align256(sizeof(double) * lbm::kDiagBlocks);
-        R.acc = (double *)p; p += align256(sizeof(double) * 8);
+        R.acc = (double *)p; p += align256(sizeof(double) * lbm::kAcc);
         R.qtab = qtab_count(R.cyl_r) ? p : nullptr; p += align256(qtab_count(R.cyl_r) * cb);
         h->runs.push_back(R);
 
@@ -528,7 +568,8 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         const RunDev &R = h->runs[r];
         std::vector<double> rho((size_t)R.nx * R.ny, R.rho_l), ux(rho.size(), R.bc_x == 1 ? cfgs[r].u_in : 0.0),
             uy(rho.size(), 0.0);
-        if ((rc = lbm_set_fields(h, r, rho.data(), ux.data(), uy.data(), nullptr)) != LBM_OK) {
+        const int seed = prec == LBM_F64_TANGENT && R.bc_x == 1 ? 1 : -1;  // d(u)/d(u_in) = 1
+        if ((rc = set_fields_impl(h, r, rho.data(), ux.data(), uy.data(), nullptr, seed)) != LBM_OK) {
             g_create_error = h->err;
             delete h;
             return rc;
@@ -539,6 +580,14 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
 }
 
 int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy, const double *T)
+{
+    return set_fields_impl(h, run, rho, ux, uy, T, -1);
+}
+
+// ux_seed_dir >= 0 (tangent precision): the x velocity field is the inlet velocity, so its
+// derivative along that direction is 1
+static int set_fields_impl(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy,
+                           const double *T, int ux_seed_dir)
 {
     int rc = check_run(h, run);
     if (rc) return rc;
@@ -555,10 +604,10 @@ int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, 
         h->pf = h->pt = h->ph = 0;
     }
     const RunDev &R = h->runs[run];
-    if ((rc = upload_plane(h, R, R.rho, rho, 0)) || (rc = upload_plane(h, R, R.ux, ux, 0)) ||
+    if ((rc = upload_plane(h, R, R.rho, rho, 0)) || (rc = upload_plane(h, R, R.ux, ux, 0, ux_seed_dir)) ||
         (rc = upload_plane(h, R, R.uy, uy, 0)) || (rc = upload_plane(h, R, R.T[0], T, R.T_sat)))
         return rc;
-    HIPCHK(h, hipMemsetAsync(R.acc, 0, sizeof(double) * 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.acc, 0, sizeof(double) * lbm::kAcc, h->stream));
     HIPCHK(h, lbm::launch_init(h->precision, h->runs_dev, run, (long long)R.nx * R.ny, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->step = 0;
@@ -674,7 +723,7 @@ int lbm_step(lbm_handle *h, int n_steps)
     }
     if (any_check) {
         for (int r = 0; r < h->n_runs; ++r) {
-            double acc[8];
+            double acc[lbm::kAcc];
             HIPCHK(h, hipMemcpyAsync(acc, h->runs[r].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
             HIPCHK(h, hipStreamSynchronize(h->stream));
             if (acc[5] != 0.0) return fail(h, LBM_EUNSTABLE, "run %d: non-finite state detected", r);
@@ -785,6 +834,37 @@ int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, doubl
     if (q_mean) *q_mean = acc[1];
     if (nu) *nu = acc[2];
     if (nu_time_avg) *nu_time_avg = acc[4] > 0 ? acc[3] / acc[4] : 0.0;
+    return LBM_OK;
+}
+
+int lbm_nu_tangent(lbm_handle *h, int run, double *dnu, double *dnu_time_avg)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (h->precision != LBM_F64_TANGENT) return fail(h, LBM_EINVAL, "the handle does not carry tangents");
+    if ((rc = moments_pass(h, run))) return rc;
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
+    double acc[lbm::kAcc];
+    HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < lbm::kTangents; ++k) {
+        if (dnu) dnu[k] = acc[8 + k];
+        if (dnu_time_avg) dnu_time_avg[k] = acc[4] > 0 ? acc[12 + k] / acc[4] : 0.0;
+    }
+    return LBM_OK;
+}
+
+int lbm_reset_time_average(lbm_handle *h, int run)
+{
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    double acc[lbm::kAcc];
+    HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    acc[3] = acc[4] = 0.0;
+    for (int k = 0; k < lbm::kTangents; ++k) acc[12 + k] = 0.0;
+    HIPCHK(h, hipMemcpyAsync(h->runs[run].acc, acc, sizeof(acc), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 

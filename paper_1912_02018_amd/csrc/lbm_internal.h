@@ -10,6 +10,13 @@ namespace lbm {
 
 constexpr int kMaxProbes = 4096;
 constexpr int kDiagBlocks = 256;
+// parameter directions of the tangent precision: superheat dTr_wall, u_in, acentric factor, tau
+constexpr int kTangents = 4;
+// FP64 accumulators per run: [0] mass, [1] q_mean, [2] Nu, [3] sum of Nu, [4] count, [5] non-finite,
+// [8 + k] dNu/dtheta_k, [12 + k] sum of dNu/dtheta_k
+constexpr int kAcc = 16;
+// probe limit of the tangent precision (its per-probe heat flux carries the tangents in LDS)
+constexpr int kMaxTangentProbes = 1024;
 
 // Per-run description read by every kernel.  Physical constants are kept in FP64 and converted
 // to the compute type inside the kernels.
@@ -27,6 +34,10 @@ struct RunDev {
     double u_in, alpha, cv, shift;
     // derived on the host: 1/sqrt(Tc), 2/(G cs^2), phi'(T) = dphi_A/sqrt(T) + dphi_B, 1/cv
     double inv_sqrt_Tc, psi_scale, dphi_A, dphi_B, inv_cv;
+    // derivatives of the parameter-dependent constants along the tangent directions (tangent
+    // precision only; zero otherwise)
+    double t_omega[kTangents], t_T_w[kTangents], t_u_in[kTangents], t_alpha[kTangents];
+    double t_kappa[kTangents], t_dphi_A[kTangents], t_dphi_B[kTangents];
     void *f[2];               // populations, storage type, [9][ny][pitch]
     void *T[2];               // temperature, compute type, [ny][pitch]
     void *rho, *ux, *uy;      // macroscopic fields of the last streamed state, compute type
@@ -34,7 +45,7 @@ struct RunDev {
     const double *probes;     // [np][2] probe coordinates
     const void *qtab;         // compute type, [2R+3][2R+3][8] wall fractions of cut links (cyl_r > 0)
     double *partials;         // [kDiagBlocks] partial mass sums
-    double *acc;              // [8]: mass, q_mean, nu, nu_sum, nu_count, nonfinite
+    double *acc;              // [kAcc]
 };
 
 // One work item: run index and tile coordinates.

@@ -27,8 +27,13 @@
 namespace lbm {
 namespace {
 
-// pointers into the workspace, in the global address space (global_load/store, not flat)
-template <typename T> using gp = __attribute__((address_space(1))) T *;
+// pointers into the workspace, in the global address space (global_load/store, not flat); class
+// types (the tangent type) keep generic pointers, whose objects can be assigned
+struct Dual;
+template <typename T> struct GlobalPtr { using type = __attribute__((address_space(1))) T *; };
+template <> struct GlobalPtr<Dual> { using type = Dual *; };
+template <> struct GlobalPtr<const Dual> { using type = const Dual *; };
+template <typename T> using gp = typename GlobalPtr<T>::type;
 template <typename T> __device__ inline gp<const T> gin(const void *p) { return (gp<const T>)p; }
 template <typename T> __device__ inline gp<T> gout(void *p) { return (gp<T>)p; }
 // element e of a workspace array, addressed with a 32-bit byte offset from a uniform base
@@ -66,6 +71,77 @@ template <> struct Ar<float> {
 };
 
 // ------------------------------------------------------------------------------------------
+// Forward-mode tangents: an FP64 value with kTangents directional derivatives.  Instantiating
+// the step with this compute (and storage) type carries d(state)/d(parameter) for every
+// parameter direction through exactly the arithmetic of the FP64 step (the value part is that
+// step's value); comparisons and branches look at the value only.
+// ------------------------------------------------------------------------------------------
+struct Dual {
+    double v, d[kTangents];
+    Dual() = default;
+    __host__ __device__ constexpr Dual(double x) : v(x), d{} {}
+    __device__ explicit operator double() const { return v; }
+};
+__device__ inline Dual operator+(const Dual &a, const Dual &b)
+{
+    Dual r; r.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+__device__ inline Dual operator-(const Dual &a, const Dual &b)
+{
+    Dual r; r.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+__device__ inline Dual operator-(const Dual &a)
+{
+    Dual r; r.v = -a.v;
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = -a.d[k];
+    return r;
+}
+__device__ inline Dual operator*(const Dual &a, const Dual &b)
+{
+    Dual r; r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+__device__ inline Dual operator/(const Dual &a, const Dual &b)
+{
+    Dual r; r.v = a.v / b.v;
+    const double ib = 1.0 / b.v;
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+    return r;
+}
+__device__ inline Dual &operator+=(Dual &a, const Dual &b) { return a = a + b; }
+__device__ inline bool operator==(const Dual &a, const Dual &b) { return a.v == b.v; }
+__device__ inline bool operator!=(const Dual &a, const Dual &b) { return a.v != b.v; }
+__device__ inline bool operator<(const Dual &a, const Dual &b) { return a.v < b.v; }
+__device__ inline bool operator>(const Dual &a, const Dual &b) { return a.v > b.v; }
+template <> struct Ar<Dual> {
+    __device__ static Dual rcp(const Dual &x)
+    {
+        Dual r; r.v = 1.0 / x.v;
+#pragma unroll
+        for (int k = 0; k < kTangents; ++k) r.d[k] = -x.d[k] * r.v * r.v;
+        return r;
+    }
+    __device__ static Dual sqrt_(const Dual &x)
+    {
+        Dual r; r.v = sqrt(x.v);
+        const double h = 0.5 / r.v;
+#pragma unroll
+        for (int k = 0; k < kTangents; ++k) r.d[k] = x.d[k] * h;
+        return r;
+    }
+};
+
+// ------------------------------------------------------------------------------------------
 // Storage type S, its raw bit type in memory, and the conversion to the compute type;
 // reduced-precision storage holds f_i - w_i rho_ref.
 template <typename S> struct Conv;
@@ -84,6 +160,11 @@ template <> struct Conv<__half> {
     __device__ static float ld(unsigned short v, float s) { return __half2float(__ushort_as_half(v)) + s; }
     __device__ static unsigned short st(float v, float s) { return __half_as_ushort(__float2half_rn(v - s)); }
 };
+template <> struct Conv<Dual> {
+    using raw = Dual;
+    __device__ static Dual ld(const Dual &v, const Dual &) { return v; }
+    __device__ static Dual st(const Dual &v, const Dual &) { return v; }
+};
 template <> struct Conv<__hip_bfloat16> {
     using raw = unsigned short;
     __device__ static float ld(unsigned short v, float s) { return __uint_as_float((unsigned)v << 16) + s; }
@@ -91,7 +172,25 @@ template <> struct Conv<__hip_bfloat16> {
 };
 template <typename S> using RawT = typename Conv<S>::raw;
 
-template <typename S> using CT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+// compute type of a storage type: FP64 and tangents compute in themselves, the rest in FP32
+template <typename S>
+using CT = typename std::conditional<std::is_same<S, double>::value || std::is_same<S, Dual>::value, S, float>::type;
+template <typename C> constexpr bool is_dual = std::is_same<C, Dual>::value;
+
+// |x| of the compute type (the tangent of |x| takes the sign of the value)
+template <typename C> __device__ inline C absval(const C &x) { return fabs(x); }
+template <> __device__ inline Dual absval<Dual>(const Dual &x) { return x.v < 0.0 ? -x : x; }
+
+// a run constant in the compute type; tangent types take its derivatives along the parameter
+// directions from the run description
+template <typename C> __device__ inline C seeded(double v, const double *) { return (C)v; }
+template <> __device__ inline Dual seeded<Dual>(double v, const double *t)
+{
+    Dual r(v);
+#pragma unroll
+    for (int k = 0; k < kTangents; ++k) r.d[k] = t[k];
+    return r;
+}
 
 // periodic wrap of a coordinate (halos may span several periods of a tiny grid)
 __device__ inline int wrap(int a, int n)
@@ -137,15 +236,15 @@ template <typename C> struct Consts {
     C shiftw[9];
     __device__ explicit Consts(const RunDev &R)
     {
-        omega = (C)R.omega; sigma = (C)R.sigma; gx = (C)R.gx; gy = (C)R.gy;
-        rho_gref = (C)R.rho_gref; rho_w = (C)R.rho_w; T_sat = (C)R.T_sat; T_w = (C)R.T_w;
-        a = (C)R.eos_a; b = (C)R.eos_b; Rg = (C)R.eos_R; u_in = (C)R.u_in;
-        alpha = (C)R.alpha; inv_cv = (C)R.inv_cv; kappa = (C)R.kappa;
+        omega = seeded<C>(R.omega, R.t_omega); sigma = (C)R.sigma; gx = (C)R.gx; gy = (C)R.gy;
+        rho_gref = (C)R.rho_gref; rho_w = (C)R.rho_w; T_sat = (C)R.T_sat; T_w = seeded<C>(R.T_w, R.t_T_w);
+        a = (C)R.eos_a; b = (C)R.eos_b; Rg = (C)R.eos_R; u_in = seeded<C>(R.u_in, R.t_u_in);
+        alpha = seeded<C>(R.alpha, R.t_alpha); inv_cv = (C)R.inv_cv; kappa = seeded<C>(R.kappa, R.t_kappa);
         inv_sqrt_Tc = (C)R.inv_sqrt_Tc;
         psi_scale = (C)R.psi_scale;
         // phi'(T) = dphi_A / sqrt(T) + dphi_B
-        dphi_A = (C)R.dphi_A;
-        dphi_B = (C)R.dphi_B;
+        dphi_A = seeded<C>(R.dphi_A, R.t_dphi_A);
+        dphi_B = seeded<C>(R.dphi_B, R.t_dphi_B);
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
@@ -695,8 +794,8 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         const C u = sm.ux[c], v = sm.uy[c];
         S.u[j] = u;
         S.v[j] = v;
-        S.au[j] = fabs(u) * cd;
-        S.av[j] = fabs(v) * cd;
+        S.au[j] = absval(u) * cd;
+        S.av[j] = absval(v) * cd;
     }
 
     Th::template stage<1>(sm, K, S);
@@ -741,39 +840,50 @@ __global__ __launch_bounds__(256) void k_diag_partial(const RunDev *__restrict__
     if (threadIdx.x == 0) R.partials[blockIdx.x] = red[0];
 }
 
+template <typename A> __device__ inline double val(const A &x) { return (double)x; }
+template <typename A> __device__ inline double der(const A &, int) { return 0.0; }
+template <> __device__ inline double der<Dual>(const Dual &x, int k) { return x.d[k]; }
+
 template <typename C>
 __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ runs, int run, int pt, int accumulate)
 {
+    // FP64 arithmetic; the tangent type carries the derivatives of Nu along
+    using A = typename std::conditional<is_dual<C>, Dual, double>::type;
+    constexpr int NQ = is_dual<C> ? kMaxTangentProbes : kMaxProbes;
     const RunDev &R = runs[run];
+    const Consts<A> K(R);
     const gp<const C> rho = gin<C>(R.rho);
     const gp<const C> T = gin<C>(R.T[pt]);
-    __shared__ double qp[kMaxProbes];
+    __shared__ A qp[NQ];
     for (int k = threadIdx.x; k < R.np; k += 256) {
         const double px = R.probes[2 * k], py = R.probes[2 * k + 1];
         const int x0 = (int)floor(px), y0 = (int)floor(py);
         const double fx = px - x0, fy = py - y0;
         const size_t i00 = (size_t)y0 * R.pitch + x0, i01 = i00 + R.pitch;
-        const double r = (1 - fx) * (1 - fy) * (double)rho[i00] + fx * (1 - fy) * (double)rho[i00 + 1] +
-                         (1 - fx) * fy * (double)rho[i01] + fx * fy * (double)rho[i01 + 1];
-        const double tp = (1 - fx) * (1 - fy) * (double)T[i00] + fx * (1 - fy) * (double)T[i00 + 1] +
-                          (1 - fx) * fy * (double)T[i01] + fx * fy * (double)T[i01 + 1];
-        qp[k] = r * R.cv * R.alpha * (R.T_w - tp) / 1.5;
+        const A w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+        const A r = w00 * (A)rho[i00] + w10 * (A)rho[i00 + 1] + w01 * (A)rho[i01] + w11 * (A)rho[i01 + 1];
+        const A tp = w00 * (A)T[i00] + w10 * (A)T[i00 + 1] + w01 * (A)T[i01] + w11 * (A)T[i01 + 1];
+        qp[k] = r * (A)R.cv * K.alpha * (K.T_w - tp) / (A)1.5;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double mass = 0.0;
         for (int b = 0; b < kDiagBlocks; ++b) mass += R.partials[b];
-        double q = 0.0;
-        for (int k = 0; k < R.np; ++k) q += qp[k];
-        q = R.np > 0 ? q / R.np : 0.0;
-        const double dT = R.T_w - R.T_sat;
-        const double nu = (R.np > 0 && dT != 0.0) ? q * 2.0 * R.cyl_r / (R.rho_v * R.cv * R.alpha * dT) : 0.0;
+        A q = 0.0;
+        for (int k = 0; k < R.np; ++k) q = q + qp[k];
+        q = R.np > 0 ? q / (A)(double)R.np : (A)0.0;
+        const A dT = K.T_w - K.T_sat;
+        const A nu = (R.np > 0 && val(dT) != 0.0)
+                         ? q * (A)2.0 * (A)(double)R.cyl_r / ((A)R.rho_v * (A)R.cv * K.alpha * dT)
+                         : (A)0.0;
         R.acc[0] = mass;
-        R.acc[1] = q;
-        R.acc[2] = nu;
+        R.acc[1] = val(q);
+        R.acc[2] = val(nu);
+        for (int k = 0; k < kTangents; ++k) R.acc[8 + k] = der(nu, k);
         if (accumulate) {
-            R.acc[3] += nu;
+            R.acc[3] += val(nu);
             R.acc[4] += 1.0;
+            for (int k = 0; k < kTangents; ++k) R.acc[12 + k] += der(nu, k);
         }
         if (!(mass == mass) || mass - mass != 0.0) R.acc[5] = 1.0;
     }
@@ -834,9 +944,14 @@ static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
 static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}, {64, 64, 1024}};
 static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
+// tangent precision (40-byte values): one small tile each (the RK4 temperature tile with its
+// 8-node halo stays within the 160 KB of LDS)
+static const Variant kTanLbm[] = {{16, 16, 256}};
+static const Variant kTanTh[] = {{16, 8, 256}};
 
 int variant_count(int precision, int kernel)
 {
+    if (precision == 4) return 1;
     if (kernel == 0) return precision == 0 ? 2 : 4;
     return precision == 0 ? 2 : 5;
 }
@@ -844,6 +959,7 @@ int variant_count(int precision, int kernel)
 Variant variant_shape(int precision, int kernel, int v)
 {
     if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0};
+    if (precision == 4) return kernel == 0 ? kTanLbm[v] : kTanTh[v];
     if (kernel == 0) return precision == 0 ? kLbm64[v] : kLbm32[v];
     return precision == 0 ? kTh64[v] : kTh32[v];
 }
@@ -862,7 +978,10 @@ static hipError_t lbm_impl(int v, bool write_f, const RunDev *runs, const Tile *
                            long long step, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    if constexpr (std::is_same<S, double>::value) {
+    if constexpr (std::is_same<S, Dual>::value) {
+        if (v != 0) return hipErrorInvalidValue;
+        return lbm_go<S, 16, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+    } else if constexpr (std::is_same<S, double>::value) {
         switch (v) {
         case 0: return lbm_go<S, 32, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
         case 1: return lbm_go<S, 16, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
@@ -887,6 +1006,7 @@ hipError_t launch_lbm(int precision, int variant, bool write_f, const RunDev *ru
     case 1: return lbm_impl<float>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
     case 2: return lbm_impl<__half>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
     case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 4: return lbm_impl<Dual>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -904,6 +1024,10 @@ hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs
                           int pt, long long step, hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
+    if (precision == 4) {
+        if (variant != 0) return hipErrorInvalidValue;
+        return th_go<Dual, 16, 8, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    }
     if (precision == 0) {
         switch (variant) {
         case 0: return th_go<double, 16, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
@@ -923,7 +1047,10 @@ hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs
 
 hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int pt, int accumulate, hipStream_t stream)
 {
-    if (precision == 0) {
+    if (precision == 4) {
+        k_diag_partial<Dual><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
+        k_diag_final<Dual><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
+    } else if (precision == 0) {
         k_diag_partial<double><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
         k_diag_final<double><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
     } else {
@@ -942,6 +1069,7 @@ hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long
     case 1: k_init<float><<<blocks, 256, 0, stream>>>(runs_dev, run); break;
     case 2: k_init<__half><<<blocks, 256, 0, stream>>>(runs_dev, run); break;
     case 3: k_init<__hip_bfloat16><<<blocks, 256, 0, stream>>>(runs_dev, run); break;
+    case 4: k_init<Dual><<<blocks, 256, 0, stream>>>(runs_dev, run); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

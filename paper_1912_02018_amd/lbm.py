@@ -36,7 +36,7 @@ EXPORTED = [
     "lbm_get_state", "lbm_set_state", "lbm_wall_heat_flux", "lbm_total_mass", "lbm_derived",
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
-    "lbm_set_option",
+    "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average",
 ]
 OPT_GRAPHS = 0
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
@@ -78,6 +78,8 @@ def load_library():
     L.lbm_wall_heat_flux.argtypes = [vp, i32, dp, dp, dp]
     L.lbm_total_mass.argtypes = [vp, i32, dp]
     L.lbm_derived.argtypes = [vp, i32, dp]
+    L.lbm_nu_tangent.argtypes = [vp, i32, dp, dp]
+    L.lbm_reset_time_average.argtypes = [vp, i32]
     L.lbm_time_kernel.argtypes = [vp, i32, i32]
     ip = C.POINTER(C.c_int)
     L.lbm_variant_count.argtypes = [i32, i32]
@@ -240,3 +242,13 @@ class Simulation:
         self._check(self._L.lbm_derived(self.h, run, _dp(out)))
         keys = ["Tc", "T_sat", "T_w", "rho_l", "rho_v", "rho_w", "rho_gref", "omega"]
         return dict(zip(keys, out.tolist()))
+
+    def nu_tangent(self, run: int = 0):
+        """(dNu/dtheta, d<Nu>_t/dtheta) of a tangent-precision run, theta = (dTr_wall, u_in,
+        acentric, tau), each a length-4 array."""
+        d, da = np.zeros(4), np.zeros(4)
+        self._check(self._L.lbm_nu_tangent(self.h, run, _dp(d), _dp(da)))
+        return d, da
+
+    def reset_time_average(self, run: int = 0):
+        self._check(self._L.lbm_reset_time_average(self.h, run))
