@@ -100,6 +100,8 @@ def main():
                     help="c2: 1024x512 boiling channel (default); c3: the same at Re 30000; sweep: 64 uneven runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c2: skip the batched-sweep, reduced-storage and HBM-resident sub-reports")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -132,7 +134,99 @@ def main():
             cfg = cfg.replace(warmup_steps=0)
         workload = f"boiling-cylinder-{cfg.nx}x{cfg.ny}-R{cfg.cyl_r}-Re{re}-rk{cfg.rk_stages}-{args.precision}"
         line = run_single(args, lbm, cfg, prec, workload, re)
+        if args.workload == "c2" and not args.no_extras:
+            line["batched_vs_single"] = sweep_summary(args, lbm)
+            line["reduced_storage"] = reduced_storage_report(lbm)
+            line["hbm_resident"] = hbm_resident_run(lbm)
     print(json.dumps(line), flush=True)
+
+
+def sweep_summary(args, lbm):
+    """Aggregate MLUPS of the 64-run superheat sweep stepped by one handle against the same runs
+    stepped one after another (shorter timing than --workload sweep)."""
+    from paper_1912_02018_amd.config import sweep_configs
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup, sub.kernel_launches = 500, 50, 20
+    rec = run_sweep(sub, lbm, sweep_configs(64, 2018, PREC["f32"]), PREC["f32"])
+    return {"workload": rec["config"]["workload"], "nodes": rec["config"]["nodes"], "mlups": rec["value"],
+            "sequential_mlups": rec["sequential_mlups"], "ratio": rec["batched_over_sequential"],
+            "steps": sub.steps}
+
+
+def reduced_storage_report(lbm, steps=1000):
+    """The Re 30000 channel (u_in 0.05) with FP64, FP32, FP16 and BF16 population storage: each
+    precision runs its own untimed 3000-step warm-up, then `steps` timed coupled steps; the final
+    fields and Nu are compared with the FP64 run (max-norm relative errors over fluid nodes; u
+    relative to max(|u|, u_in))."""
+    import numpy as np
+    import torch
+    from paper_1912_02018_amd.config import config3
+    ref, out = None, {}
+    rho_l = None
+    cases = (("f64", "f64", None), ("f32", "f32", None), ("f16s_shift_1", "f16s", 1.0),
+             ("f16s_shift_rho_l", "f16s", "rho_l"), ("bf16s_shift_rho_l", "bf16s", "rho_l"))
+    for label, pname, shift in cases:
+        cfg = config3(PREC[pname])
+        if shift == "rho_l":
+            cfg = cfg.replace(rho_ref_shift=rho_l)
+        elif shift is not None:
+            cfg = cfg.replace(rho_ref_shift=shift)
+        sim = lbm.Simulation(cfg)
+        if rho_l is None:
+            rho_l = sim.derived()["rho_l"]
+        sim.step(cfg.warmup_steps)
+        sim.autotune(10)
+        ms, _ = timed_steps(torch, sim, steps)
+        f = sim.fields()
+        _, nu, _ = sim.wall_heat_flux()
+        rec = {"mlups": round(cfg.nx * cfg.ny / (ms / steps * 1e-3) / 1e6, 1)}
+        if shift is not None:
+            rec["rho_ref_shift"] = round(float(cfg.rho_ref_shift), 6)
+        if ref is None:
+            ref = (f, nu)
+        else:
+            g, nu0 = ref
+            fl = g["mask"] == 0
+            rel = lambda a, b: float(np.abs(a - b)[fl].max() / np.abs(b)[fl].max())
+            du = np.hypot(f["ux"] - g["ux"], f["uy"] - g["uy"])[fl].max()
+            umax = max(float(np.hypot(g["ux"], g["uy"])[fl].max()), cfg.u_in)
+            rec["err_vs_f64"] = {"rho": rel(f["rho"], g["rho"]), "u": float(du / umax),
+                                 "T": rel(f["T"], g["T"]), "nu": abs(nu / nu0 - 1.0)}
+        out[label] = rec
+        sim.close()
+    return {"workload": "boiling-cylinder-1024x512-R32-Re30000-rk4", "steps_after_warmup": steps, **out}
+
+
+def hbm_resident_run(lbm, steps=200):
+    """The Re 300 channel scaled by 8 (8192x4096, cylinder R 256 at x 2048): a state of ~3 GB that
+    no cache holds.  Coupled steps from the initial liquid state (no physical warm-up; the same
+    per-step work)."""
+    import torch
+    from paper_1912_02018_amd.config import cylinder_config
+    cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=PREC["f32"],
+                          warmup=0)
+    sim = lbm.Simulation(cfg)
+    sim.step(10)
+    sim.autotune(5)
+    sim.step(10)
+    ms, _ = timed_steps(torch, sim, steps)
+    nodes = cfg.nx * cfg.ny
+    mlups = nodes / (ms / steps * 1e-3) / 1e6
+    kt = {}
+    for k in (0, 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.time_kernel(k, 20)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        kt[KERNEL_NAMES[k]] = e0.elapsed_time(e1) / 20
+    rec = {"workload": "boiling-cylinder-8192x4096-R256-Re300-rk4-f32", "nodes": nodes, "mlups": round(mlups, 1),
+           "ms_per_step": round(ms / steps, 4), "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
+           "kernel_hbm_gbs": {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, PREC["f32"]) * nodes / (kt[KERNEL_NAMES[k]] * 1e-3) / 1e9, 1)
+                              for k in (0, 1)},
+           "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}}
+    sim.close()
+    return rec
 
 
 def timed_steps(torch, sim, steps):

@@ -191,6 +191,53 @@ def test_fp32_error_after_1000_steps(lbm_mod):
     compare(sim, ref, "fp32 vs oracle cylinder 1000 steps", tol=1e-4, tol_u=1e-3, u_ref=cfg32.u_in)
 
 
+# Reduced-precision storage (FP32 compute, populations stored as f_i - w_i rho_ref in FP16 or BF16)
+# after 1000 steps of a 256x128 channel (R 8, no warm-up) against the FP64 oracle.  Storage rounding
+# has relative spacing 2^-11 (FP16) or 2^-8 (BF16) on f_i - w_i rho_ref; with rho_ref = rho_l the
+# liquid's populations keep most of their bits, with rho_ref = 1 (f_i - w_i) they do not.  The bounds
+# are three times the errors measured on MI355X (rho, u, T: max-norm relative over fluid nodes, u
+# relative to max(|u|, u_in); Nu: relative).
+STORAGE_BOUNDS = {
+    # (Re, precision, shift): (rho, u, T, Nu)
+    (30000.0, "f16", "rho_l"): (1.5e-3, 1.5e-2, 2e-3, 1e-4),
+    (30000.0, "f16", "one"): (4e-2, 2e-1, 4e-2, 2e-3),
+    (30000.0, "bf16", "rho_l"): (2e-2, 1.5e-1, 2.5e-2, 1.2e-2),
+    (300.0, "f16", "rho_l"): (7e-4, 6e-3, 6e-4, 1.2e-4),
+    (300.0, "bf16", "rho_l"): (2e-2, 1.2e-1, 1.5e-2, 1.5e-2),
+}
+
+
+@pytest.mark.parametrize("re,u_in", [(30000.0, 0.05), (300.0, 0.02)])
+def test_reduced_precision_storage_error_bounds(lbm_mod, re, u_in):
+    from paper_1912_02018_amd.config import FP16S, BF16S
+    rl, rv = coex()
+    base = cylinder_config(256, 128, 8, 64, re=re, u_in=u_in, dTr_wall=0.1, precision=FP64, warmup=0,
+                           diag_every=10).replace(rho_l=rl, rho_v=rv)
+    ref = oracle.Sim(base)
+    ref.step(1000)
+    o = ref.fields()
+    fl = o["mask"] == 0
+    nu0 = ref.wall_heat_flux()[1]
+    errs = {}
+    for (r, pname, shift), bounds in STORAGE_BOUNDS.items():
+        if r != re:
+            continue
+        prec = FP16S if pname == "f16" else BF16S
+        sim = lbm_mod.Simulation(base.replace(precision=prec, rho_ref_shift=rl if shift == "rho_l" else 1.0))
+        sim.step(1000)
+        g = sim.fields()
+        du = np.hypot(g["ux"] - o["ux"], g["uy"] - o["uy"])[fl].max()
+        e = (rel(g["rho"][fl], o["rho"][fl]), float(du / max(np.hypot(o["ux"], o["uy"])[fl].max(), u_in)),
+             rel(g["T"][fl], o["T"][fl]), abs(sim.wall_heat_flux()[1] / nu0 - 1.0))
+        errs[(pname, shift)] = e
+        print(f"Re {re:g} {pname} shift {shift}: rho {e[0]:.2e} u {e[1]:.2e} T {e[2]:.2e} Nu {e[3]:.2e}", flush=True)
+        for name, v, b in zip(("rho", "u", "T", "Nu"), e, bounds):
+            assert v <= b, (re, pname, shift, name, v, b)
+    if ("f16", "one") in errs:
+        # shifting by w_i rho_l rather than w_i keeps the liquid's precision
+        assert errs[("f16", "rho_l")][0] * 5 <= errs[("f16", "one")][0]
+
+
 def test_graph_replay_matches_eager_bitwise(lbm_mod):
     """Steps replayed from captured HIP graphs equal directly launched steps bit for bit, over
     several replays separated by eager work (field read-back, heat-flux reductions)."""
