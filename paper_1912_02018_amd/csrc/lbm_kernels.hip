@@ -604,7 +604,9 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
 // wavefronts drop out as the stages shrink.
 template <int TX, int TY, int NS> struct ThGeom {
     static constexpr int H = 2 * NS;
-    static constexpr int RW = TX + 2 * H, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
+    // region of RX x RH positions stored with an odd row stride RW (the ring slots of a wavefront
+    // are short row pieces a stride apart, which an even stride would put on few LDS banks)
+    static constexpr int RX = TX + 2 * H, RW = RX + 1, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
     static constexpr int count(int s) { return (TX + 4 * (NS - s)) * (TY + 4 * (NS - s)); }
     static constexpr int NSLOT = count(1);
 };
@@ -723,7 +725,8 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
                                                 long long step)
 {
     using Th = Thermal<C, TX, TY, NS, NT>;
-    constexpr int H = Th::H, RW = Th::RW, RN = Th::RN, TN = Th::TN, NSLOT = Th::NSLOT, ITER = Th::ITER;
+    constexpr int H = Th::H, RX = Th::G::RX, RW = Th::RW, RH = Th::G::RH, TN = Th::TN, NSLOT = Th::NSLOT;
+    constexpr int ITER = Th::ITER;
     __shared__ typename Th::Smem sm;
 
     const Tile t = tiles[blockIdx.x];
@@ -743,8 +746,8 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
     const Consts<C> K(R);
 
     // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
-    for (int p = threadIdx.x; p < RN; p += NT) {
-        const int lx = p % RW, ly = p / RW;
+    for (int n = threadIdx.x; n < RX * RH; n += NT) {
+        const int lx = n % RX, ly = n / RX, p = ly * RW + lx;
         int rx, ry;
         const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
         const unsigned idx = (unsigned)(ry * P + rx);
