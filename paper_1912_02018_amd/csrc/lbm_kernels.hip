@@ -233,6 +233,7 @@ __device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
 template <typename C> struct Consts {
     C omega, sigma, gx, gy, rho_gref, rho_w, T_sat, T_w, a, b, Rg, u_in;
     C alpha, inv_cv, kappa, inv_sqrt_Tc, psi_scale, dphi_A, dphi_B;
+    C alpha2w1, alpha2w2, alpha2w4, alpha2w5, alpha2w8, alpha2wsum;  // 2 alpha w_k, 2 alpha sum_k w_k
     C shiftw[9];
     __device__ explicit Consts(const RunDev &R)
     {
@@ -245,6 +246,8 @@ template <typename C> struct Consts {
         // phi'(T) = dphi_A / sqrt(T) + dphi_B
         dphi_A = seeded<C>(R.dphi_A, R.t_dphi_A);
         dphi_B = seeded<C>(R.dphi_B, R.t_dphi_B);
+        alpha2w1 = (C)(2.0 * W1) * alpha; alpha2w2 = (C)(2.0 * W2) * alpha; alpha2w4 = (C)(2.0 * W4) * alpha;
+        alpha2w5 = (C)(2.0 * W5) * alpha; alpha2w8 = (C)(2.0 * W8) * alpha; alpha2wsum = (C)(2.0 * WSUM) * alpha;
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
@@ -649,7 +652,14 @@ template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
     struct Slots {
         int own[ITER];  // LDS position of the slot
         int ev[ITER];   // LDS position the operator is evaluated at; < 0: value held (solid, inlet ghost)
-        C T0[ITER], acc[ITER], u[ITER], v[ITER], au[ITER], av[ITER], gx[ITER], gy[ITER], c1[ITER], c2[ITER];
+        C T0[ITER], acc[ITER];
+        // L(Y) = sum over the axis pairs (+-1, 0), (+-2, 0), (0, +-1), (0, +-2) of cS * (sum of the
+        // pair) + cd * (difference of the pair), + 2 alpha w_k (sum of the pair) over the diagonal
+        // pairs, + gx, gy times the diagonal part of the isotropic gradient, + c0 Y + c2 sqrt(Y):
+        // the Laplacian, the density-gradient term, the upwind convection and the source with the
+        // slot's own coefficients folded in
+        C cS10[ITER], cS20[ITER], cd10[ITER], cd20[ITER], cS01[ITER], cS02[ITER], cd01[ITER], cd02[ITER];
+        C gx[ITER], gy[ITER], c0[ITER], c2[ITER];
     };
 
     // right-hand side L(Y) of eq. energy at LDS position c with the coefficients of slot j
@@ -672,18 +682,20 @@ template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
 #undef Y_
         d.d11 = a11 - b11; d.d1m = a1m - b1m; d.d21 = a21 - b21; d.d2m = a2m - b2m;
         d.d12 = a12 - b12; d.d1m2 = a1m2 - b1m2; d.d22 = a22 - b22; d.d2m2 = a2m2 - b2m2;
-        // isotropic Laplacian 2 sum_k w_k (Y(x + e_k) - Y(x))
-        const C lap = (C)2 * ((C)W1 * (S10 + S01) + (C)W2 * ((a11 + b11) + (a1m + b1m)) + (C)W4 * (S20 + S02) +
-                              (C)W5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
-                              (C)W8 * ((a22 + b22) + (a2m2 + b2m2))) -
-                      (C)(2.0 * WSUM) * y0;
-        // third-order upwind-biased convection (au, av: |u| times the dissipation coefficient)
-        const C conv = S.u[j] * ((C)8 * d.d10 - d.d20) * (C)(1.0 / 12.0) + S.au[j] * (S20 - (C)4 * S10 + (C)6 * y0) +
-                       S.v[j] * ((C)8 * d.d01 - d.d02) * (C)(1.0 / 12.0) + S.av[j] * (S02 - (C)4 * S01 + (C)6 * y0);
-        const C diff = K.alpha * lap + S.gx[j] * d.gx() + S.gy[j] * d.gy();
-        // pressure-work source T (c1 + c2 phi'(T)) with phi'(T) = A / sqrt(T) + B
-        const C src = S.c1[j] * y0 + S.c2[j] * Ar<C>::sqrt_(y0);
-        return diff + src - conv;
+        // axis pairs: Laplacian, upwind convection and the axis part of the gradient term
+        const C ax = S.cS10[j] * S10 + S.cS20[j] * S20 + S.cd10[j] * d.d10 + S.cd20[j] * d.d20 + S.cS01[j] * S01 +
+                     S.cS02[j] * S02 + S.cd01[j] * d.d01 + S.cd02[j] * d.d02;
+        // diagonal pairs: Laplacian (2 alpha w_k) and the diagonal part of the gradient term
+        const C dg = K.alpha2w2 * ((a11 + b11) + (a1m + b1m)) +
+                     K.alpha2w5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
+                     K.alpha2w8 * ((a22 + b22) + (a2m2 + b2m2));
+        const C gdx = (C)W2 * (d.d11 + d.d1m) + (C)W5 * ((C)2 * (d.d21 + d.d2m) + d.d12 + d.d1m2) +
+                      (C)(2 * W8) * (d.d22 + d.d2m2);
+        const C gdy = (C)W2 * (d.d11 - d.d1m) + (C)W5 * (d.d21 - d.d2m + (C)2 * (d.d12 - d.d1m2)) +
+                      (C)(2 * W8) * (d.d22 - d.d2m2);
+        // centre: Laplacian, convection and the linear part of the pressure-work source
+        // T (c1 + c2 phi'(T)), phi'(T) = A / sqrt(T) + B
+        return ax + dg + S.gx[j] * gdx + S.gy[j] * gdy + S.c0[j] * y0 + S.c2[j] * Ar<C>::sqrt_(y0);
     }
 
     // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input
@@ -768,7 +780,8 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
 #pragma unroll
     for (int j = 0; j < ITER; ++j) {
         S.own[j] = 0; S.ev[j] = -1;
-        S.T0[j] = S.acc[j] = S.u[j] = S.v[j] = S.au[j] = S.av[j] = S.gx[j] = S.gy[j] = S.c1[j] = S.c2[j] = 0;
+        S.T0[j] = S.acc[j] = S.gx[j] = S.gy[j] = S.c0[j] = S.c2[j] = 0;
+        S.cS10[j] = S.cS20[j] = S.cd10[j] = S.cd20[j] = S.cS01[j] = S.cS02[j] = S.cd01[j] = S.cd02[j] = 0;
         const int r = threadIdx.x + NT * j;
         if (r >= NSLOT) continue;
         const int p = kSlots<TX, TY, NS>.pos[r];
@@ -786,19 +799,30 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         const PairD<C> dv = pair_diffs<RW>(sm.uy, c);
         const C rho = sm.rho[c];
         const C ir = Ar<C>::rcp(rho);
-        S.gx[j] = K.alpha * dr.gx() * ir;
-        S.gy[j] = K.alpha * dr.gy() * ir;
+        const C gx = K.alpha * dr.gx() * ir;
+        const C gy = K.alpha * dr.gy() * ir;
         const C D = (du.gx() + dv.gy()) * ir * K.inv_cv;
         const C d1 = (C)1 - K.b * rho;
         const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
         const C A2 = D * K.a * rho * rho * Ar<C>::rcp(d2);
-        S.c1[j] = -D * rho * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
+        const C c1 = -D * rho * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
         S.c2[j] = K.dphi_A * A2;
+        // third-order upwind-biased convection per axis:
+        //   u (8 d1 - d2) / 12 + |u| c_d (S2 - 4 S1 + 6 Y)   (d, S: differences / sums of the pair)
         const C u = sm.ux[c], v = sm.uy[c];
-        S.u[j] = u;
-        S.v[j] = v;
-        S.au[j] = absval(u) * cd;
-        S.av[j] = absval(v) * cd;
+        const C au = absval(u) * cd, av = absval(v) * cd;
+        const C u12 = u * (C)(1.0 / 12.0), v12 = v * (C)(1.0 / 12.0);
+        S.gx[j] = gx;
+        S.gy[j] = gy;
+        S.cS10[j] = K.alpha2w1 + (C)4 * au;
+        S.cS20[j] = K.alpha2w4 - au;
+        S.cd10[j] = (C)W1 * gx - (C)8 * u12;
+        S.cd20[j] = (C)(2 * W4) * gx + u12;
+        S.cS01[j] = K.alpha2w1 + (C)4 * av;
+        S.cS02[j] = K.alpha2w4 - av;
+        S.cd01[j] = (C)W1 * gy - (C)8 * v12;
+        S.cd02[j] = (C)(2 * W4) * gy + v12;
+        S.c0[j] = c1 - K.alpha2wsum - (C)6 * (au + av);
     }
 
     Th::template stage<1>(sm, K, S);
