@@ -138,6 +138,7 @@ def main():
             line["batched_vs_single"] = sweep_summary(args, lbm)
             line["reduced_storage"] = reduced_storage_report(lbm)
             line["hbm_resident"] = hbm_resident_run(lbm)
+            line["sensitivity"] = sensitivity_run(lbm)
     print(json.dumps(line), flush=True)
 
 
@@ -146,7 +147,7 @@ def sweep_summary(args, lbm):
     stepped one after another (shorter timing than --workload sweep)."""
     from paper_1912_02018_amd.config import sweep_configs
     sub = argparse.Namespace(**vars(args))
-    sub.steps, sub.warmup, sub.kernel_launches = 500, 50, 20
+    sub.steps, sub.warmup, sub.kernel_launches = 1000, 100, 20
     rec = run_sweep(sub, lbm, sweep_configs(64, 2018, PREC["f32"]), PREC["f32"])
     return {"workload": rec["config"]["workload"], "nodes": rec["config"]["nodes"], "mlups": rec["value"],
             "sequential_mlups": rec["sequential_mlups"], "ratio": rec["batched_over_sequential"],
@@ -195,6 +196,25 @@ def reduced_storage_report(lbm, steps=1000):
         out[label] = rec
         sim.close()
     return {"workload": "boiling-cylinder-1024x512-R32-Re30000-rk4", "steps_after_warmup": steps, **out}
+
+
+def sensitivity_run(lbm, steps=4000, average_from=2000):
+    """Time-averaged Nu of the 512x256 channel (R 16, Re 300, superheat 0.1 T_c, no warm-up) over
+    steps 2000..3999 and its gradient with respect to (superheat, u_in, acentric factor, tau), from
+    one run of the forward-mode tangent precision (FP64 values + 4 derivatives per value)."""
+    import torch
+    from paper_1912_02018_amd import sensitivity
+    from paper_1912_02018_amd.config import config5
+    cfg = sensitivity.hold_coexistence(config5(PREC["f64"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = sensitivity.nu_average_and_gradient(cfg, steps, average_from)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "boiling-cylinder-512x256-R16-Re300-rk4-f64-tangent4", "steps": steps,
+            "average_from": average_from, "J_mean_nu": J,
+            "dJ_dtheta": dict(zip(sensitivity.TANGENT_PARAMS, [float(x) for x in g])),
+            "wall_s": round(dt, 3), "mlups_incl_setup": round(cfg.nx * cfg.ny * steps / dt / 1e6, 1)}
 
 
 def hbm_resident_run(lbm, steps=200):

@@ -67,3 +67,29 @@ def test_invalid_configs_rejected(bad):
 def test_mixed_precision_batch_rejected():
     with pytest.raises(lbm.LBMError):
         lbm.workspace_bytes([config5(), config5().replace(precision=0)])
+
+
+def test_empty_batch_and_maximum_grid():
+    """No runs: rejected.  The largest grids are bounded by 32-bit byte offsets within the 9
+    population planes (9 ny pitch storage_bytes < 2^32): a 2^14 x 2^13 FP32 grid (4.5 GiB of
+    populations) is rejected, 2^14 x 2^12 (2.25 GiB) is sized."""
+    with pytest.raises(lbm.LBMError):
+        lbm.workspace_bytes([])
+    big = LBMConfig(nx=1 << 14, ny=1 << 13, bc_x=0, alpha_T=0.01, precision=1)
+    with pytest.raises(lbm.LBMError):
+        lbm.workspace_bytes([big])
+    ok = big.replace(ny=1 << 12)
+    assert lbm.workspace_bytes([ok]) >= 2 * 9 * 4 * (1 << 26)
+
+
+def test_tangent_precision_sizing():
+    """LBM_F64_TANGENT stores 5 FP64 numbers per value (value + 4 derivatives)."""
+    from paper_1912_02018_amd.config import F64_TANGENT
+    c64 = config5(0)
+    b64 = lbm.workspace_bytes([c64])
+    bt = lbm.workspace_bytes([c64.replace(precision=F64_TANGENT)])
+    assert 4.5 * b64 < bt < 5.5 * b64
+    # the per-probe heat fluxes of the tangent reduction live in LDS: large cylinders are refused
+    with pytest.raises(lbm.LBMError):
+        lbm.workspace_bytes([LBMConfig(nx=2048, ny=1024, cyl_x=600, cyl_y=512, cyl_r=420, alpha_T=0.01,
+                                       precision=F64_TANGENT)])

@@ -286,3 +286,27 @@ def test_autotune_keeps_results(lbm_mod):
     a.step(50)
     b.step(50)
     assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
+
+
+def test_degenerate_cases(lbm_mod):
+    """Uniform saturated liquid at rest in a periodic box stays at rest (equilibrium is a fixed
+    point of the collision, psi is uniform so the force vanishes, and T_sat is a steady state of
+    the temperature equation); with zero superheat the cylinder reports Nu = 0 (no division by
+    the zero temperature difference)."""
+    rl, rv = coex()
+    cfg = LBMConfig(nx=48, ny=40, bc_x=BC_PERIODIC, rk_stages=4, nu=0.1, alpha_T=0.05, rho_l=rl, rho_v=rv,
+                    precision=FP64)
+    sim = lbm_mod.Simulation(cfg)
+    sim.step(100)
+    f = sim.fields()
+    assert np.abs(f["rho"] - rl).max() <= 1e-13 * rl
+    assert np.hypot(f["ux"], f["uy"]).max() <= 1e-14
+    Tsat = sim.derived()["T_sat"]
+    assert np.abs(f["T"] - Tsat).max() <= 1e-15
+    cyl = cylinder_config(96, 48, 6, 24, re=30.0, u_in=0.02, dTr_wall=0.0, precision=FP64, warmup=0,
+                          diag_every=1).replace(rho_l=rl, rho_v=rv)
+    sim = lbm_mod.Simulation(cyl)
+    sim.step(20)
+    q, nu, nua = sim.wall_heat_flux()
+    assert nu == 0.0 and nua == 0.0
+    assert np.isfinite(q)
