@@ -149,6 +149,15 @@ int lbm_reset_time_average(lbm_handle *h, int run);
 /* FP64 sum of rho over the fluid nodes of the current state.  Waits for the stream. */
 int lbm_total_mass(lbm_handle *h, int run, double *mass);
 
+/* Saturation state of a configuration's Peng-Robinson fluid (eq. eos; host only, no device
+ * needed): out6 = [T_c, T_sat, p_sat, rho_l, rho_v, h_fg].  T_c = 0.0778 a / (0.4572 b R); the
+ * coexistence densities follow the Maxwell equal-area construction in specific volume (Sec. III D);
+ * the latent heat h_fg = T_sat (s_v - s_l), with the entropy difference integrated from the
+ * Maxwell relation (ds/dv)_T = (dp/dT)_v of the EOS (equivalent to Clausius-Clapeyron on the
+ * saturation curve).  Uses eos_a, eos_b, eos_R, acentric and Tr_sat of *cfg.  LBM_EINVAL if there
+ * is no coexistence (see lbm_last_error(NULL)). */
+int lbm_saturation(const lbm_config *cfg, double *out6);
+
 /* Derived constants of a run: [Tc, T_sat, T_w, rho_l, rho_v, rho_w, rho_gref, omega]. */
 int lbm_derived(lbm_handle *h, int run, double *out8);
 

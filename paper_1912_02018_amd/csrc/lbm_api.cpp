@@ -881,6 +881,30 @@ int lbm_total_mass(lbm_handle *h, int run, double *mass)
     return LBM_OK;
 }
 
+int lbm_saturation(const lbm_config *cfg, double *out6)
+{
+    if (!cfg || !out6) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (!(cfg->eos_a > 0) || !(cfg->eos_b > 0) || !(cfg->eos_R > 0) || !(cfg->Tr_sat > 0 && cfg->Tr_sat < 1))
+        return fail(nullptr, LBM_EINVAL, "EOS constants out of range");
+    const PR pr(*cfg);
+    const double T = cfg->Tr_sat * pr.Tc;
+    double rv, rl;
+    if (!maxwell(pr, T, rv, rl)) return fail(nullptr, LBM_EINVAL, "no liquid-vapour coexistence at T_sat");
+    const double vl = 1.0 / rl, vv = 1.0 / rv, b = pr.b, s2 = std::sqrt(2.0);
+    // h_fg = T (s_v - s_l) with s_v - s_l = int_{v_l}^{v_v} (dp/dT)_v dv (a Maxwell relation), and
+    // (dp/dT)_v = R/(v - b) - a phi'(T)/(v^2 + 2bv - b^2), phi'(T) = -kappa (1 + kappa (1 - sqrt(T/Tc))) / sqrt(T Tc)
+    const double dphi = -pr.kappa * (1.0 + pr.kappa * (1.0 - std::sqrt(T / pr.Tc))) / std::sqrt(T * pr.Tc);
+    auto I = [&](double v) { return std::log((v + b - s2 * b) / (v + b + s2 * b)) / (2.0 * s2 * b); };
+    const double ds = pr.R * std::log((vv - b) / (vl - b)) - pr.a * dphi * (I(vv) - I(vl));
+    out6[0] = pr.Tc;
+    out6[1] = T;
+    out6[2] = pr.p_v(vv, T);
+    out6[3] = rl;
+    out6[4] = rv;
+    out6[5] = T * ds;
+    return LBM_OK;
+}
+
 int lbm_derived(lbm_handle *h, int run, double *out8)
 {
     int rc = check_run(h, run);

@@ -36,7 +36,7 @@ EXPORTED = [
     "lbm_get_state", "lbm_set_state", "lbm_wall_heat_flux", "lbm_total_mass", "lbm_derived",
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
-    "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average",
+    "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation",
 ]
 OPT_GRAPHS = 0
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
@@ -79,6 +79,7 @@ def load_library():
     L.lbm_total_mass.argtypes = [vp, i32, dp]
     L.lbm_derived.argtypes = [vp, i32, dp]
     L.lbm_nu_tangent.argtypes = [vp, i32, dp, dp]
+    L.lbm_saturation.argtypes = [cfgp, dp]
     L.lbm_reset_time_average.argtypes = [vp, i32]
     L.lbm_time_kernel.argtypes = [vp, i32, i32]
     ip = C.POINTER(C.c_int)
@@ -119,6 +120,16 @@ def workspace_bytes(cfgs: Sequence[LBMConfig]) -> int:
     if n == 0:
         raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
     return n
+
+
+def saturation(cfg: LBMConfig) -> dict:
+    """Saturation state of the configuration's Peng-Robinson fluid at Tr_sat (host computation)."""
+    L = load_library()
+    out = np.zeros(6)
+    c = to_c_config(cfg)
+    if L.lbm_saturation(C.byref(c), _dp(out)) != LBM_OK:
+        raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
+    return dict(zip(["Tc", "T_sat", "p_sat", "rho_l", "rho_v", "h_fg"], out.tolist()))
 
 
 class Simulation:
