@@ -56,12 +56,16 @@ enum {
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_BF16S = 3, LBM_F64_TANGENT = 4 };
 enum { LBM_TANGENTS = 4 };
 
-/* x boundaries; y is always periodic */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_INLET_OUTLET = 1 };
+/* x boundaries; y is always periodic.  LBM_BC_INLET_OUTLET: Zou-He velocity inlet (u_in, 0) at
+ * x = 0 and convective outlet (speed u_in) at x = nx-1 (Sec. IV A).  LBM_BC_WALL_OUTLET: heated
+ * no-slip wall at x = -1/2 (halfway bounce-back; T = T_w, and behind it rho_wall, u = 0 like the
+ * cylinder's solid nodes) with the same convective outlet: the Stefan problem (Sec. III E).  The
+ * default state of a wall run is at rest.  FP64 and FP32 only. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_INLET_OUTLET = 1, LBM_BC_WALL_OUTLET = 2 };
 
 typedef struct {
     int32_t nx, ny;         /* grid (>= 4 each) */
-    int32_t bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INLET_OUTLET */
+    int32_t bc_x;           /* LBM_BC_PERIODIC, LBM_BC_INLET_OUTLET or LBM_BC_WALL_OUTLET */
     int32_t rk_stages;      /* temperature update: 0 none, 2 Heun, 4 classical RK4 */
     int32_t warmup_steps;   /* first steps with neither forcing nor temperature update (Sec. IV A) */
     int32_t cyl_x, cyl_y, cyl_r; /* cylinder centre / radius in lattice units; cyl_r <= 0: none.
@@ -84,6 +88,12 @@ typedef struct {
     int32_t precision;      /* LBM_FP64 ... LBM_F64_TANGENT; all runs of a handle share it */
     int32_t check_every;    /* > 0: lbm_step checks the state for non-finite values */
     double rho_ref_shift;   /* reduced-precision storage offset rho_ref (f_i - w_i rho_ref) */
+    double nu_vapor;        /* > 0: phase-dependent viscosity: nu is the liquid value, nu_vapor the
+                               vapour's, linear in rho between rho_v and rho_l (constant outside);
+                               <= 0: nu everywhere.  FP64 and FP32 only. */
+    double alpha_vapor;     /* > 0: phase-dependent thermal diffusivity, likewise with alpha_T the
+                               liquid value; lambda = rho c_v alpha(rho) in the energy equation and
+                               lambda_v = rho_v c_v alpha_vapor in Nu.  <= 0: alpha_T everywhere. */
 } lbm_config;
 
 /* Bytes of device workspace needed for n_runs runs (cfgs[0..n_runs-1]); 0 on invalid input. */

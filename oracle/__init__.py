@@ -28,6 +28,7 @@ PARAM_FIELDS = [
     ("G", C.c_double), ("sigma", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
     ("rho_gref", C.c_double), ("rho_l", C.c_double), ("rho_v", C.c_double),
     ("rho_wall", C.c_double), ("u_in", C.c_double), ("alpha_T", C.c_double), ("cv", C.c_double),
+    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double),
 ]
 
 

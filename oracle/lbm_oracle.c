@@ -39,7 +39,8 @@
 /* ------------------------------------------------------------------------------------------ */
 typedef struct {
     int32_t nx, ny;
-    int32_t bc_x;         /* 0: periodic in x; 1: velocity inlet at x=0, convective outlet at x=nx-1 */
+    int32_t bc_x;         /* 0: periodic in x; 1: velocity inlet at x=0, convective outlet at x=nx-1;
+                             2: heated no-slip wall at x=-1/2 (T_w), convective outlet at x=nx-1 */
     int32_t rk_stages;    /* 0: isothermal, 2: Heun, 4: classical RK4 */
     int32_t warmup_steps; /* steps with neither forcing nor temperature update */
     int32_t cyl_x, cyl_y, cyl_r; /* cylinder centre and radius (lattice units); r <= 0: none */
@@ -55,8 +56,10 @@ typedef struct {
     double rho_l, rho_v;  /* coexistence densities; <= 0 selects the Maxwell construction */
     double rho_wall;      /* density given to solid nodes; <= 0 selects rho_l */
     double u_in;          /* inlet velocity */
-    double alpha_T;       /* thermal diffusivity */
+    double alpha_T;       /* thermal diffusivity (of the liquid when the vapour value is set) */
     double cv;            /* specific heat at constant volume */
+    double nu_vapor;      /* vapour kinematic viscosity; <= 0: nu in both phases */
+    double alpha_vapor;   /* vapour thermal diffusivity; <= 0: alpha_T in both phases */
 } orc_params;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -378,19 +381,58 @@ static int is_solid_xy(const orc_sim *s, int x, int y)
 int orc_is_solid(const orc_sim *s, int x, int y) { return is_solid_xy(s, x, y); }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Phase-dependent transport properties (reading of the steam-table property ratios): nu and   */
+/* alpha vary linearly in density between the vapour and liquid coexistence densities, held   */
+/* constant outside; nu = p->nu and alpha = p->alpha_T are the liquid values.                  */
+/* ------------------------------------------------------------------------------------------ */
+static double phase_frac(const orc_sim *s, double rho, int *inside)
+{
+    double t = (rho - s->rho_v) / (s->rho_l - s->rho_v);
+    *inside = t > 0.0 && t < 1.0;
+    return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+}
+
+static double nu_at(const orc_sim *s, double rho)
+{
+    if (s->p.nu_vapor <= 0.0) return s->p.nu;
+    int in;
+    double t = phase_frac(s, rho, &in);
+    return s->p.nu_vapor + t * (s->p.nu - s->p.nu_vapor);
+}
+
+static double alpha_at(const orc_sim *s, double rho)
+{
+    if (s->p.alpha_vapor <= 0.0) return s->p.alpha_T;
+    int in;
+    double t = phase_frac(s, rho, &in);
+    return s->p.alpha_vapor + t * (s->p.alpha_T - s->p.alpha_vapor);
+}
+
+static double dalpha_drho(const orc_sim *s, double rho)
+{
+    if (s->p.alpha_vapor <= 0.0) return 0.0;
+    int in;
+    phase_frac(s, rho, &in);
+    return in ? (s->p.alpha_T - s->p.alpha_vapor) / (s->rho_l - s->rho_v) : 0.0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Field extension (reading): solid nodes carry rho_w, u = 0, T_w (stored directly in the      */
 /* arrays); y is periodic; x is periodic, or ghost columns x < 0 copy rho and u of column 0    */
-/* with T = T_sat (inlet), and x >= nx copy column nx-1 (outlet).                              */
+/* with T = T_sat (inlet), or behind a wall (bc 2) carry rho_w, u = 0, T_w like solid nodes,   */
+/* and x >= nx copy column nx-1 (outlet).                                                      */
 /* ------------------------------------------------------------------------------------------ */
-static int ext_index(const orc_sim *s, int x, int y, int *inlet_ghost)
+enum { EXT_NODE = 0, EXT_INLET = 1, EXT_WALL = 2 };
+
+static int ext_index(const orc_sim *s, int x, int y, int *kind)
 {
     int yy = wrapi(y, s->ny), xx;
-    *inlet_ghost = 0;
+    *kind = EXT_NODE;
     if (s->p.bc_x == 0) {
         xx = wrapi(x, s->nx);
     } else if (x < 0) {
         xx = 0;
-        *inlet_ghost = 1;
+        *kind = s->p.bc_x == 2 ? EXT_WALL : EXT_INLET;
     } else if (x >= s->nx) {
         xx = s->nx - 1;
     } else {
@@ -399,17 +441,19 @@ static int ext_index(const orc_sim *s, int x, int y, int *inlet_ghost)
     return yy * s->nx + xx;
 }
 
-static double ext_scalar(const orc_sim *s, const double *a, int x, int y)
+/* rho (wall_value = rho_w) or a velocity component (wall_value = 0) on the extended field */
+static double ext_scalar(const orc_sim *s, const double *a, int x, int y, double wall_value)
 {
     int g;
-    return a[ext_index(s, x, y, &g)];
+    int k = ext_index(s, x, y, &g);
+    return g == EXT_WALL ? wall_value : a[k];
 }
 
 static double ext_temperature(const orc_sim *s, const double *a, int x, int y)
 {
     int g;
     int k = ext_index(s, x, y, &g);
-    return g ? s->T_sat : a[k];
+    return g == EXT_INLET ? s->T_sat : (g == EXT_WALL ? s->T_w : a[k]);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -475,7 +519,7 @@ orc_sim *orc_create(const orc_params *p)
     /* default initial state (reading of the garbled initial-condition sentence): saturated
      * liquid at T_sat moving with the inlet velocity; solid nodes at T_w */
     double *r0 = alloc_d(n), *u0 = alloc_d(n), *v0 = alloc_d(n), *t0 = alloc_d(n);
-    for (size_t k = 0; k < n; ++k) { r0[k] = s->rho_l; u0[k] = p->bc_x ? p->u_in : 0.0; v0[k] = 0.0; t0[k] = s->T_sat; }
+    for (size_t k = 0; k < n; ++k) { r0[k] = s->rho_l; u0[k] = p->bc_x == 1 ? p->u_in : 0.0; v0[k] = 0.0; t0[k] = s->T_sat; }
     orc_set_fields(s, r0, u0, v0, t0);
     free(r0); free(u0); free(v0); free(t0);
     return s;
@@ -616,10 +660,10 @@ static void stream_all(orc_sim *s, double *new_hist)
             }
             for (int i = 0; i < 9; ++i) {
                 int xs = x - CX[i];
-                if (s->p.bc_x == 1 && (xs < 0 || xs >= nx)) { f[i] = 0.0; continue; }
+                if (s->p.bc_x != 0 && (xs < 0 || xs >= nx)) { f[i] = 0.0; continue; }
                 f[i] = pull_interior(s, i, x, y);
             }
-            if (s->p.bc_x == 1 && x == nx - 1) {
+            if (s->p.bc_x != 0 && x == nx - 1) {
                 for (int m = 0; m < 3; ++m) {
                     int i = OUT_DIRS[m];
                     double prev_col = pull_interior(s, i, nx - 2, y);
@@ -627,10 +671,14 @@ static void stream_all(orc_sim *s, double *new_hist)
                 }
             }
             if (s->p.bc_x == 1 && x == 0) orc_zou_he(s->p.u_in, f);
+            /* halfway bounce-back on the wall at x = -1/2: what left towards it returns reversed */
+            if (s->p.bc_x == 2 && x == 0)
+                for (int i = 1; i < 9; ++i)
+                    if (CX[i] > 0) f[i] = fstar_at(s, OPP[i], 0, y);
             for (int i = 0; i < 9; ++i) s->f[(size_t)i * n + k] = f[i];
         }
     }
-    if (s->p.bc_x == 1) {
+    if (s->p.bc_x != 0) {
         for (int y = 0; y < ny; ++y) {
             int k = y * nx + nx - 1;
             new_hist[0 * ny + y] = s->f[(size_t)2 * n + k];
@@ -685,7 +733,8 @@ static void macroscopic(orc_sim *s)
                         if (ex == 0 && ey == 0) continue;
                         int g;
                         int kk = ext_index(s, x + ex, y + ey, &g);
-                        double ps = g ? orc_psi(p, s->rho[kk], s->T_sat) : s->psi[kk];
+                        double ps = g == EXT_INLET ? orc_psi(p, s->rho[kk], s->T_sat)
+                                  : (g == EXT_WALL ? orc_psi(p, s->rho_w, s->T_w) : s->psi[kk]);
                         double w = stencil_w(ex * ex + ey * ey);
                         sx += w * ps * ex;
                         sy += w * ps * ey;
@@ -722,9 +771,9 @@ static void thermal_frozen(orc_sim *s)
                 for (int ex = -2; ex <= 2; ++ex) {
                     if (ex == 0 && ey == 0) continue;
                     double w = stencil_w(ex * ex + ey * ey);
-                    gx += w * ext_scalar(s, s->rho, x + ex, y + ey) * ex;
-                    gy += w * ext_scalar(s, s->rho, x + ex, y + ey) * ey;
-                    dv += w * (ext_scalar(s, s->ux, x + ex, y + ey) * ex + ext_scalar(s, s->uy, x + ex, y + ey) * ey);
+                    gx += w * ext_scalar(s, s->rho, x + ex, y + ey, s->rho_w) * ex;
+                    gy += w * ext_scalar(s, s->rho, x + ex, y + ey, s->rho_w) * ey;
+                    dv += w * (ext_scalar(s, s->ux, x + ex, y + ey, 0.0) * ex + ext_scalar(s, s->uy, x + ex, y + ey, 0.0) * ey);
                 }
             s->gradrx[k] = gx; s->gradry[k] = gy; s->divu[k] = dv;
         }
@@ -761,7 +810,10 @@ static void thermal_rhs(orc_sim *s, const double *Y, double *L)
                     lap += 2.0 * w * (yn - y0);
                 }
             /* (1/(rho cv)) div(lambda grad T) with lambda = rho cv alpha (reading) */
-            double diff = p->alpha_T * (lap + (s->gradrx[k] * gx + s->gradry[k] * gy) / r);
+            /* with lambda = rho cv alpha(rho): (1/(rho cv)) div(lambda grad T)
+             *   = alpha (lap T + grad rho . grad T / rho) + alpha'(rho) grad rho . grad T */
+            double gg = s->gradrx[k] * gx + s->gradry[k] * gy;
+            double diff = alpha_at(s, r) * (lap + gg / r) + dalpha_drho(s, r) * gg;
             /* pressure-work (latent heat) source */
             double src = -y0 / (r * p->cv) * orc_eos_dpdT(p, r, y0) * s->divu[k];
             L[k] = -conv + diff + src;
@@ -816,12 +868,12 @@ static void heat_flux_from_fields(const orc_sim *s, double *q_mean, double *nu)
     for (int k = 0; k < s->np; ++k) {
         double rp = bilinear(s, s->rho, s->probe_x[k], s->probe_y[k]);
         double tp = bilinear(s, s->T, s->probe_x[k], s->probe_y[k]);
-        qs += rp * p->cv * p->alpha_T * (s->T_w - tp) / 1.5;
+        qs += rp * p->cv * alpha_at(s, rp) * (s->T_w - tp) / 1.5;
     }
     double q = qs / s->np;
     double dT = s->T_w - s->T_sat;
     *q_mean = q;
-    *nu = dT != 0.0 ? q * 2.0 * p->cyl_r / (s->rho_v * p->cv * p->alpha_T * dT) : 0.0;
+    *nu = dT != 0.0 ? q * 2.0 * p->cyl_r / (s->rho_v * p->cv * alpha_at(s, s->rho_v) * dT) : 0.0;
 }
 
 /* evaluate macroscopic fields of the current state (streams into the work arrays) */
@@ -854,7 +906,8 @@ static void one_step(orc_sim *s)
         if (s->solid[k]) continue;
         double f[9], fs[9];
         for (int i = 0; i < 9; ++i) f[i] = s->f[(size_t)i * n + k];
-        orc_collide_node(s->omega, fon ? s->p.sigma : 0.0, f, s->rho[k], s->ux[k], s->uy[k], s->Fx[k], s->Fy[k], s->Fm2p[k], fs);
+        double om = s->p.nu_vapor > 0.0 ? 1.0 / (nu_at(s, s->rho[k]) / CS2 + 0.5) : s->omega;
+        orc_collide_node(om, fon ? s->p.sigma : 0.0, f, s->rho[k], s->ux[k], s->uy[k], s->Fx[k], s->Fy[k], s->Fm2p[k], fs);
         for (int i = 0; i < 9; ++i) s->fstar[(size_t)i * n + k] = fs[i];
     }
     if (fon && s->p.rk_stages > 0) thermal_update(s);

@@ -20,7 +20,7 @@ PRECISION_NAMES = {FP64: "f64", FP32: "f32", FP16S: "f16-store", BF16S: "bf16-st
                    F64_TANGENT: "f64+tangents"}
 # parameter directions of the tangent precision (order of lbm_nu_tangent)
 TANGENT_PARAMS = ("dTr_wall", "u_in", "acentric", "tau")
-BC_PERIODIC, BC_INLET_OUTLET = 0, 1
+BC_PERIODIC, BC_INLET_OUTLET, BC_WALL_OUTLET = 0, 1, 2
 
 
 @dataclass
@@ -56,6 +56,8 @@ class LBMConfig:
     precision: int = FP64
     check_every: int = 0         # > 0: lbm_step reports non-finite state
     rho_ref_shift: float = 1.0   # reduced-precision storage holds f_i - w_i * rho_ref_shift
+    nu_vapor: float = 0.0        # > 0: vapour viscosity (nu is then the liquid's), linear in density between
+    alpha_vapor: float = 0.0     # > 0: vapour thermal diffusivity (alpha_T the liquid's), same interpolation
 
     def replace(self, **kw) -> "LBMConfig":
         return dataclasses.replace(self, **kw)

@@ -39,6 +39,7 @@ struct lbm_handle {
     std::vector<int> lbm_off, lbm_cnt, th_off, th_cnt;
     int n_lbm = 0, n_th = 0;
     int var[2] = {0, 0};              // launch variant of k_lbm, k_thermal
+    bool phase = false;               // some run has phase-dependent transport or a heated wall
     int pf = 0, pt = 0, ph = 0;
     long long step = 0;
     bool use_graphs = true;
@@ -162,8 +163,11 @@ int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
         if (k.nx < 4 || k.ny < 4) return fail(h, LBM_EINVAL, "run %d: grid must be at least 4x4", r);
         if (9.0 * k.ny * pitch_of(k.nx) * storage_bytes(k.precision) >= 4294967296.0)
             return fail(h, LBM_EINVAL, "run %d: grid too large (9 population planes must stay below 4 GiB)", r);
-        if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET) return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
+        if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET && k.bc_x != LBM_BC_WALL_OUTLET)
+            return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
         if (k.precision < 0 || k.precision > 4) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
+        if (k.precision >= 2 && (k.nu_vapor > 0 || k.alpha_vapor > 0 || k.bc_x == LBM_BC_WALL_OUTLET))
+            return fail(h, LBM_EINVAL, "run %d: phase-dependent transport and the heated wall need FP64 or FP32", r);
         if (k.precision == 4 && probe_count(k.cyl_r) > lbm::kMaxTangentProbes)
             return fail(h, LBM_EINVAL, "run %d: cylinder too large for the tangent precision", r);
         if (k.precision != c[0].precision) return fail(h, LBM_EINVAL, "all runs must share one precision");
@@ -419,7 +423,7 @@ int download_plane(lbm_handle *h, const RunDev &R, const void *src, std::vector<
 // macroscopic pass of one run without collision (writes rho, ux, uy of the current state)
 int moments_pass(lbm_handle *h, int run)
 {
-    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], false, h->runs_dev, h->tiles_lbm + h->lbm_off[run],
+    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], false, h->phase, h->runs_dev, h->tiles_lbm + h->lbm_off[run],
                               h->lbm_cnt[run], h->pf, h->pt, h->ph, h->step, h->stream));
     return LBM_OK;
 }
@@ -485,12 +489,18 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
             }
         }
         R.rho_l = rl; R.rho_v = rv;
+        R.inv_drho = 1.0 / (rl - rv);
         R.rho_w = k.rho_wall > 0 ? k.rho_wall : rl;
         R.rho_gref = k.rho_gref >= 0 ? k.rho_gref : rl;
         R.omega = 1.0 / (k.nu / (1.0 / 3.0) + 0.5);
         R.sigma = k.sigma; R.G = k.G; R.gx = k.gx; R.gy = k.gy;
         R.eos_a = k.eos_a; R.eos_b = k.eos_b; R.eos_R = k.eos_R;
         R.u_in = k.u_in; R.alpha = k.alpha_T; R.cv = k.cv;
+        R.phase_props = (k.nu_vapor > 0 || k.alpha_vapor > 0) ? 1 : 0;
+        h->phase |= R.phase_props != 0 || R.bc_x == LBM_BC_WALL_OUTLET;
+        R.nu_l = k.nu;
+        R.nu_v = k.nu_vapor > 0 ? k.nu_vapor : k.nu;
+        R.alpha_v = k.alpha_vapor > 0 ? k.alpha_vapor : k.alpha_T;
         R.shift = prec >= 2 ? k.rho_ref_shift : 0.0;
         R.inv_sqrt_Tc = 1.0 / std::sqrt(R.Tc);
         R.psi_scale = 2.0 / (R.G * (1.0 / 3.0));
@@ -617,7 +627,7 @@ static int set_fields_impl(lbm_handle *h, int run, const double *rho, const doub
 // Enqueue the launches of one step (no host synchronisation).
 static int enqueue_step(lbm_handle *h)
 {
-    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
+    HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
                               h->step, h->stream));
     bool thermal = false;
     for (int r = 0; r < h->n_runs; ++r) {
@@ -629,7 +639,7 @@ static int enqueue_step(lbm_handle *h)
         thermal |= fon && k.rk_stages > 0;
     }
     if (thermal) {
-        HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
+        HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
                                       h->stream));
         h->pt ^= 1;
     }
@@ -922,14 +932,14 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
     if (n_launches < 0) return fail(h, LBM_EINVAL, "negative launch count");
     if (kernel == LBM_KERNEL_STREAM_COLLIDE) {
         for (int k = 0; k < n_launches; ++k)
-            HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt,
+            HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt,
                                       h->ph, h->step, h->stream));
         return LBM_OK;
     }
     if (kernel == LBM_KERNEL_THERMAL) {
         if (h->rk == 0) return fail(h, LBM_EINVAL, "runs have no temperature update");
         for (int k = 0; k < n_launches; ++k)
-            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->runs_dev, h->tiles_th, h->n_th, h->pt,
+            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th, h->n_th, h->pt,
                                           std::max<long long>(h->step, max_warmup(h)), h->stream));
         return LBM_OK;
     }

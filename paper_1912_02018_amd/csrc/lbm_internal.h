@@ -32,6 +32,10 @@ struct RunDev {
     double omega, sigma, G, gx, gy, rho_gref, rho_w, rho_l, rho_v;
     double T_sat, T_w, Tc, kappa, eos_a, eos_b, eos_R;
     double u_in, alpha, cv, shift;
+    // phase-dependent transport (phase_props != 0): nu and alpha linear in rho between the vapour
+    // (rho_v) and liquid (rho_l) values, held outside; alpha above is then the liquid value
+    int phase_props, pad1;
+    double nu_l, nu_v, alpha_v, inv_drho;   // inv_drho = 1 / (rho_l - rho_v)
     // derived on the host: 1/sqrt(Tc), 2/(G cs^2), phi'(T) = dphi_A/sqrt(T) + dphi_B, 1/cv
     double inv_sqrt_Tc, psi_scale, dphi_A, dphi_B, inv_cv;
     // derivatives of the parameter-dependent constants along the tangent directions (tangent
@@ -64,10 +68,12 @@ Variant variant_shape(int precision, int kernel, int v);
 
 // Launchers (each enqueues on `stream`; returns a hipError_t).
 hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream);
-hipError_t launch_lbm(int precision, int variant, bool write_f, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                      int parity_f, int parity_t, int parity_h, long long step, hipStream_t stream);
-hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                          int parity_t, long long step, hipStream_t stream);
+// phase: some run of the launch has phase-dependent transport or a heated wall (FP32 / FP64
+// only); the kernels without these features are launched otherwise
+hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, const RunDev *runs_dev, const Tile *tiles,
+                      int n_tiles, int parity_f, int parity_t, int parity_h, long long step, hipStream_t stream);
+hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
+                          int n_tiles, int parity_t, long long step, hipStream_t stream);
 hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int parity_t, int accumulate,
                        hipStream_t stream);
 

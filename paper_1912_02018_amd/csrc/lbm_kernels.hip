@@ -211,17 +211,20 @@ __device__ inline bool solid_at(const RunDev &R, int x, int y)
 }
 
 // Position kinds of the extended field: a node of the domain, an inlet ghost column (x < 0,
-// rho/u of column 0, T = T_sat) or an outlet ghost column (x >= nx, copy of column nx-1).
-enum { NODE = 0, INLET_GHOST = 1, OUTLET_GHOST = 2 };
+// rho/u of column 0, T = T_sat), a ghost behind the heated wall (x < 0 with the wall boundary:
+// rho_w, u = 0, T_w, like a solid node) or an outlet ghost column (x >= nx, copy of column nx-1).
+enum { NODE = 0, INLET_GHOST = 1, OUTLET_GHOST = 2, WALL_GHOST = 3 };
 
-__device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
+// (EXT: launches that carry the extended features, heated walls and phase-dependent properties;
+// without it their code is absent)
+template <bool EXT = true> __device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
 {
     ry = wrap(gy, R.ny);
     if (R.bc_x == 0) {
         rx = wrap(gx, R.nx);
         return NODE;
     }
-    if (gx < 0) { rx = 0; return INLET_GHOST; }
+    if (gx < 0) { rx = 0; return (EXT && R.bc_x == 2) ? WALL_GHOST : INLET_GHOST; }
     if (gx >= R.nx) { rx = R.nx - 1; return OUTLET_GHOST; }
     rx = gx;
     return NODE;
@@ -233,7 +236,7 @@ __device__ inline int map_pos(const RunDev &R, int gx, int gy, int &rx, int &ry)
 template <typename C> struct Consts {
     C omega, sigma, gx, gy, rho_gref, rho_w, T_sat, T_w, a, b, Rg, u_in;
     C alpha, inv_cv, kappa, inv_sqrt_Tc, psi_scale, dphi_A, dphi_B;
-    C alpha2w1, alpha2w2, alpha2w4, alpha2w5, alpha2w8, alpha2wsum;  // 2 alpha w_k, 2 alpha sum_k w_k
+    C alpha2w2, alpha2w5, alpha2w8;  // 2 alpha w_k of the diagonal stencil classes
     C shiftw[9];
     __device__ explicit Consts(const RunDev &R)
     {
@@ -246,8 +249,7 @@ template <typename C> struct Consts {
         // phi'(T) = dphi_A / sqrt(T) + dphi_B
         dphi_A = seeded<C>(R.dphi_A, R.t_dphi_A);
         dphi_B = seeded<C>(R.dphi_B, R.t_dphi_B);
-        alpha2w1 = (C)(2.0 * W1) * alpha; alpha2w2 = (C)(2.0 * W2) * alpha; alpha2w4 = (C)(2.0 * W4) * alpha;
-        alpha2w5 = (C)(2.0 * W5) * alpha; alpha2w8 = (C)(2.0 * W8) * alpha; alpha2wsum = (C)(2.0 * WSUM) * alpha;
+        alpha2w2 = (C)(2.0 * W2) * alpha; alpha2w5 = (C)(2.0 * W5) * alpha; alpha2w8 = (C)(2.0 * W8) * alpha;
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
@@ -262,6 +264,40 @@ template <typename C> __device__ inline C pseudopotential(const Consts<C> &K, C 
     const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
     const C p = (rho * K.Rg * T * d2 - K.a * phi * rho * rho * d1) * Ar<C>::rcp(d1 * d2);
     return Ar<C>::sqrt_((p - rho * (C)(1.0 / 3.0)) * K.psi_scale);
+}
+
+// Phase-dependent transport (runs with phase_props): nu and alpha linear in density between the
+// vapour and liquid coexistence densities, held constant outside that range.  PH: the launch
+// carries the extended features (phase-dependent transport, heated walls); without it their code
+// is compiled out.
+template <typename C> __device__ inline C phase_frac(const RunDev &R, C rho, bool &inside)
+{
+    const C t = (rho - (C)R.rho_v) * (C)R.inv_drho;
+    inside = t > (C)0 && t < (C)1;
+    return t < (C)0 ? (C)0 : (t > (C)1 ? (C)1 : t);
+}
+// relaxation rate of the shear moments at density rho: 1 / (nu(rho) / cs^2 + 1/2)
+template <bool PH, typename C> __device__ inline C omega_at(const RunDev &R, const Consts<C> &K, C rho)
+{
+    if constexpr (!PH) {
+        return K.omega;
+    } else {
+        if (!R.phase_props) return K.omega;
+        bool in;
+        const C nu = (C)R.nu_v + phase_frac(R, rho, in) * (C)(R.nu_l - R.nu_v);
+        return Ar<C>::rcp(nu * (C)3 + (C)0.5);
+    }
+}
+// thermal diffusivity and its density derivative at density rho
+template <bool PH, typename C> __device__ inline C alpha_at(const RunDev &R, const Consts<C> &K, C rho, C &dalpha)
+{
+    dalpha = (C)0;
+    if (!PH || !R.phase_props) return K.alpha;
+    bool in;
+    const C t = phase_frac(R, rho, in);
+    const C span = (C)(R.alpha - R.alpha_v);
+    if (in) dalpha = span * (C)R.inv_drho;
+    return (C)R.alpha_v + t * span;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -281,7 +317,7 @@ __device__ inline C ldf(const char *base, unsigned plane, unsigned pitch, int i,
 // the domain are clamped in (apply_x_bc then replaces the inlet's unknowns; at the outlet the clamped
 // values are the ones the convective condition needs).  Offsets are formed once per node: one row
 // product, neighbouring rows and columns by adds and selects.
-template <typename S, typename C>
+template <typename S, typename C, bool EXT = true>
 __device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
     constexpr unsigned es = (unsigned)sizeof(RawT<S>);
@@ -294,11 +330,20 @@ __device__ inline void pull_bulk(const RunDev &R, const Consts<C> &K, const char
     const unsigned c0 = (unsigned)x * es;
     const unsigned cm = x == 0 ? (periodic ? (unsigned)(nx - 1) * es : 0u) : c0 - es;
     const unsigned cp = x == nx - 1 ? (periodic ? 0u : c0) : c0 + es;
+    // next to the heated wall at x = -1/2 (halfway bounce-back) the populations entering along
+    // +x are the node's own outgoing ones reversed: f_i(0, y) = f*_opp(i)(0, y)
+    const bool wall = EXT && R.bc_x == 2 && x == 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const unsigned row = cy_of(i) > 0 ? rm : (cy_of(i) < 0 ? rp : r0);
+        unsigned row = cy_of(i) > 0 ? rm : (cy_of(i) < 0 ? rp : r0);
         const unsigned col = cx_of(i) > 0 ? cm : (cx_of(i) < 0 ? cp : c0);
-        f[i] = Conv<S>::ld(*(gp<const RawT<S>>)(fin + ((unsigned)i * planeB + row + col)), K.shiftw[i]);
+        unsigned plane = (unsigned)i * planeB;
+        if (cx_of(i) > 0) {
+            row = wall ? r0 : row;
+            plane = wall ? (unsigned)opp_of(i) * planeB : plane;
+        }
+        // (opposite directions share the lattice weight, so the storage shift of i applies)
+        f[i] = Conv<S>::ld(*(gp<const RawT<S>>)(fin + (plane + row + col)), K.shiftw[i]);
     }
 }
 
@@ -342,7 +387,8 @@ __device__ inline void fix_near(const RunDev &R, const Consts<C> &K, const char 
     }
 }
 
-// Velocity inlet at x = 0 and convective outlet at x = nx - 1.
+// Velocity inlet at x = 0 and convective outlet at x = nx - 1 (the heated wall's bounce-back is
+// part of the plain pulls).
 template <typename S, typename C>
 __device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, gp<const C> hin, int x, int y, C f[9])
 {
@@ -358,7 +404,7 @@ __device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, gp<const 
         f[6] = (hin[1 * ny + y] + U * p6) * inv;
         f[8] = (hin[2 * ny + y] + U * p8) * inv;
     }
-    if (x == 0) {
+    if (x == 0 && R.bc_x != 2) {
         // velocity inlet (u_in, 0): unknowns 1, 5, 7
         const C u = K.u_in;
         const C rin = (f[0] + f[3] + f[4] + (C)2 * (f[2] + f[6] + f[8])) * Ar<C>::rcp((C)1 - u);
@@ -374,7 +420,7 @@ __device__ inline void fix_special(const RunDev &R, const Consts<C> &K, const ch
                                    C f[9])
 {
     if (near_cylinder(R, x, y)) fix_near<S, C>(R, K, fin, x, y, f);
-    if (R.bc_x == 1 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, gin<C>(hin), x, y, f);
+    if (R.bc_x != 0 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, gin<C>(hin), x, y, f);
 }
 
 // An index the optimiser cannot re-associate with the constant offsets added to it afterwards,
@@ -427,7 +473,7 @@ template <int RW, typename C> __device__ inline PairD<C> pair_diffs(const C *s, 
 // ------------------------------------------------------------------------------------------
 // k_lbm: streaming + moments + psi + force + central-moment collision
 // ------------------------------------------------------------------------------------------
-template <typename S, int TX, int TY, int NT, bool WRITE_F>
+template <typename S, int TX, int TY, int NT, bool WRITE_F, bool PH>
 __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pf,
                                             int pt, int ph, long long step)
 {
@@ -464,16 +510,16 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
         const bool own = lx >= H && lx < H + TX && ly >= H && ly < H + TY && gx < nx && gy < ny;
         if (!fon && !own) continue;
         int rx, ry;
-        const int kind = map_pos(R, gx, gy, rx, ry);
+        const int kind = map_pos<PH>(R, gx, gy, rx, ry);
         rxv[j] = rx;
         ryv[j] = ry;
         need |= 1u << j;
         if (kind == INLET_GHOST) inlet |= 1u << j;
-        if (solid_at(R, rx, ry)) {
+        if (kind == WALL_GHOST || solid_at(R, rx, ry)) {
             solid |= 1u << j;
             continue;
         }
-        pull_bulk<S, C>(R, K, fin, rx, ry, fv[j]);
+        pull_bulk<S, C, PH>(R, K, fin, rx, ry, fv[j]);
         Tv[j] = ld_at<C>(R.T[pt], (unsigned)(ry * P + rx));
     }
 #pragma unroll
@@ -492,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
             if (own) { s_m[0][q] = rho; s_m[1][q] = 0; s_m[2][q] = 0; s_m[3][q] = 0; s_m[4][q] = 0; }
         } else {
             C *f = fv[j];
-            if (near_cylinder(R, rx, ry) || (R.bc_x == 1 && (rx == 0 || rx == nx - 1)))
+            if (near_cylinder(R, rx, ry) || (R.bc_x != 0 && (rx == 0 || rx == nx - 1)))
                 fix_special<S, C>(R, K, fin, R.hist[ph], rx, ry, f);
             rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
             T = ((inlet >> j) & 1u) ? K.T_sat : Tv[j];
@@ -502,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
                 s_m[2][q] = (f[3] - f[4]) + (f[5] - f[6]) + (f[8] - f[7]);
                 s_m[3][q] = (f[1] + f[2]) - (f[3] + f[4]);
                 s_m[4][q] = (f[5] + f[6]) - (f[7] + f[8]);
-                if (WRITE_F && R.bc_x == 1 && gx == nx - 1) {
+                if (WRITE_F && R.bc_x != 0 && gx == nx - 1) {
                     hout[0 * ny + gy] = f[2];
                     hout[1 * ny + gy] = f[6];
                     hout[2 * ny + gy] = f[8];
@@ -562,7 +608,8 @@ __global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, con
         // post-collision central moments (eq. postColl2)
         const C k0 = rho, k1 = (C)0.5 * Fx, k2 = (C)0.5 * Fy;
         const C k3 = (C)(2.0 / 3.0) * rho + A;
-        const C k4s = ((C)1 - K.omega) * k4, k5s = ((C)1 - K.omega) * k5;
+        const C om = omega_at<PH>(R, K, rho);
+        const C k4s = ((C)1 - om) * k4, k5s = ((C)1 - om) * k5;
         const C k6 = Fy * (C)(1.0 / 6.0), k7 = Fx * (C)(1.0 / 6.0);
         const C k8 = rho * (C)(1.0 / 9.0) + A * (C)(1.0 / 3.0);
         // raw moments m* = N(-u) k*
@@ -640,7 +687,7 @@ template <int TX, int TY, int NS> constexpr SlotTable<TX, TY, NS> make_slots()
 
 template <int TX, int TY, int NS> __constant__ const SlotTable<TX, TY, NS> kSlots = make_slots<TX, TY, NS>();
 
-template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
+template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     using G = ThGeom<TX, TY, NS>;
     static constexpr int H = G::H, RW = G::RW, RN = G::RN, TN = G::TN, NSLOT = G::NSLOT;
     static constexpr int ITER = (NSLOT + NT - 1) / NT;
@@ -660,6 +707,7 @@ template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
         // slot's own coefficients folded in
         C cS10[ITER], cS20[ITER], cd10[ITER], cd20[ITER], cS01[ITER], cS02[ITER], cd01[ITER], cd02[ITER];
         C gx[ITER], gy[ITER], c0[ITER], c2[ITER];
+        C al[PH ? ITER : 1];  // alpha at the slot (phase-dependent properties)
     };
 
     // right-hand side L(Y) of eq. energy at LDS position c with the coefficients of slot j
@@ -686,9 +734,14 @@ template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
         const C ax = S.cS10[j] * S10 + S.cS20[j] * S20 + S.cd10[j] * d.d10 + S.cd20[j] * d.d20 + S.cS01[j] * S01 +
                      S.cS02[j] * S02 + S.cd01[j] * d.d01 + S.cd02[j] * d.d02;
         // diagonal pairs: Laplacian (2 alpha w_k) and the diagonal part of the gradient term
-        const C dg = K.alpha2w2 * ((a11 + b11) + (a1m + b1m)) +
-                     K.alpha2w5 * (((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2))) +
-                     K.alpha2w8 * ((a22 + b22) + (a2m2 + b2m2));
+        const C s2 = (a11 + b11) + (a1m + b1m);
+        const C s5 = ((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2));
+        const C s8 = (a22 + b22) + (a2m2 + b2m2);
+        C dg;
+        if constexpr (PH)
+            dg = S.al[j] * ((C)(2 * W2) * s2 + (C)(2 * W5) * s5 + (C)(2 * W8) * s8);
+        else
+            dg = K.alpha2w2 * s2 + K.alpha2w5 * s5 + K.alpha2w8 * s8;
         const C gdx = (C)W2 * (d.d11 + d.d1m) + (C)W5 * ((C)2 * (d.d21 + d.d2m) + d.d12 + d.d1m2) +
                       (C)(2 * W8) * (d.d22 + d.d2m2);
         const C gdy = (C)W2 * (d.d11 - d.d1m) + (C)W5 * (d.d21 - d.d2m + (C)2 * (d.d12 - d.d1m2)) +
@@ -732,11 +785,11 @@ template <typename C, int TX, int TY, int NS, int NT> struct Thermal {
     }
 };
 
-template <typename C, int TX, int TY, int NS, int NT>
+template <typename C, int TX, int TY, int NS, int NT, bool PH>
 __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt,
                                                 long long step)
 {
-    using Th = Thermal<C, TX, TY, NS, NT>;
+    using Th = Thermal<C, TX, TY, NS, NT, PH>;
     constexpr int H = Th::H, RX = Th::G::RX, RW = Th::RW, RH = Th::G::RH, TN = Th::TN, NSLOT = Th::NSLOT;
     constexpr int ITER = Th::ITER;
     __shared__ typename Th::Smem sm;
@@ -761,12 +814,13 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
     for (int n = threadIdx.x; n < RX * RH; n += NT) {
         const int lx = n % RX, ly = n / RX, p = ly * RW + lx;
         int rx, ry;
-        const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
         const unsigned idx = (unsigned)(ry * P + rx);
-        sm.rho[p] = ld_at<C>(R.rho, idx);
-        sm.ux[p] = ld_at<C>(R.ux, idx);
-        sm.uy[p] = ld_at<C>(R.uy, idx);
-        sm.Y[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
+        const bool wall = PH && kind == WALL_GHOST;
+        sm.rho[p] = wall ? K.rho_w : ld_at<C>(R.rho, idx);
+        sm.ux[p] = wall ? (C)0 : ld_at<C>(R.ux, idx);
+        sm.uy[p] = wall ? (C)0 : ld_at<C>(R.uy, idx);
+        sm.Y[p] = kind == INLET_GHOST ? K.T_sat : (wall ? K.T_w : ld_at<C>(R.T[pt], idx));
     }
     __syncthreads();
 
@@ -781,16 +835,17 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
     for (int j = 0; j < ITER; ++j) {
         S.own[j] = 0; S.ev[j] = -1;
         S.T0[j] = S.acc[j] = S.gx[j] = S.gy[j] = S.c0[j] = S.c2[j] = 0;
+        if constexpr (PH) S.al[j] = 0;
         S.cS10[j] = S.cS20[j] = S.cd10[j] = S.cd20[j] = S.cS01[j] = S.cS02[j] = S.cd01[j] = S.cd02[j] = 0;
         const int r = threadIdx.x + NT * j;
         if (r >= NSLOT) continue;
         const int p = kSlots<TX, TY, NS>.pos[r];
         const int lx = p % RW, ly = p / RW;
         int rx, ry;
-        const int kind = map_pos(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
         S.own[j] = p;
         S.T0[j] = sm.Y[p];
-        if (kind == INLET_GHOST || solid_at(R, rx, ry)) continue;
+        if (kind == INLET_GHOST || kind == WALL_GHOST || solid_at(R, rx, ry)) continue;
         // an outlet ghost evaluates the operator at the last column of its row
         const int c = kind == OUTLET_GHOST ? ly * RW + out_c : p;
         S.ev[j] = c;
@@ -799,8 +854,13 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         const PairD<C> dv = pair_diffs<RW>(sm.uy, c);
         const C rho = sm.rho[c];
         const C ir = Ar<C>::rcp(rho);
-        const C gx = K.alpha * dr.gx() * ir;
-        const C gy = K.alpha * dr.gy() * ir;
+        // (1/(rho cv)) div(lambda grad T) with lambda = rho cv alpha(rho):
+        //   alpha (lap T + grad rho . grad T / rho) + alpha'(rho) grad rho . grad T
+        C dal;
+        const C al = alpha_at<PH>(R, K, rho, dal);
+        const C gcoef = al * ir + dal;
+        const C gx = gcoef * dr.gx();
+        const C gy = gcoef * dr.gy();
         const C D = (du.gx() + dv.gy()) * ir * K.inv_cv;
         const C d1 = (C)1 - K.b * rho;
         const C d2 = (C)1 + (C)2 * K.b * rho - K.b * K.b * rho * rho;
@@ -814,15 +874,17 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         const C u12 = u * (C)(1.0 / 12.0), v12 = v * (C)(1.0 / 12.0);
         S.gx[j] = gx;
         S.gy[j] = gy;
-        S.cS10[j] = K.alpha2w1 + (C)4 * au;
-        S.cS20[j] = K.alpha2w4 - au;
+        const C a2w1 = (C)(2 * W1) * al, a2w4 = (C)(2 * W4) * al;
+        if constexpr (PH) S.al[j] = al;
+        S.cS10[j] = a2w1 + (C)4 * au;
+        S.cS20[j] = a2w4 - au;
         S.cd10[j] = (C)W1 * gx - (C)8 * u12;
         S.cd20[j] = (C)(2 * W4) * gx + u12;
-        S.cS01[j] = K.alpha2w1 + (C)4 * av;
-        S.cS02[j] = K.alpha2w4 - av;
+        S.cS01[j] = a2w1 + (C)4 * av;
+        S.cS02[j] = a2w4 - av;
         S.cd01[j] = (C)W1 * gy - (C)8 * v12;
         S.cd02[j] = (C)(2 * W4) * gy + v12;
-        S.c0[j] = c1 - K.alpha2wsum - (C)6 * (au + av);
+        S.c0[j] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
     }
 
     Th::template stage<1>(sm, K, S);
@@ -871,6 +933,12 @@ template <typename A> __device__ inline double val(const A &x) { return (double)
 template <typename A> __device__ inline double der(const A &, int) { return 0.0; }
 template <> __device__ inline double der<Dual>(const Dual &x, int k) { return x.d[k]; }
 
+// thermal diffusivity of the vapour (lambda_v = rho_v c_v alpha_v normalises Nu)
+template <typename A> __device__ inline A vapour_alpha(const RunDev &R, const Consts<A> &K)
+{
+    return R.phase_props ? (A)R.alpha_v : K.alpha;
+}
+
 template <typename C>
 __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ runs, int run, int pt, int accumulate)
 {
@@ -890,7 +958,8 @@ __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ r
         const A w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
         const A r = w00 * (A)rho[i00] + w10 * (A)rho[i00 + 1] + w01 * (A)rho[i01] + w11 * (A)rho[i01 + 1];
         const A tp = w00 * (A)T[i00] + w10 * (A)T[i00 + 1] + w01 * (A)T[i01] + w11 * (A)T[i01 + 1];
-        qp[k] = r * (A)R.cv * K.alpha * (K.T_w - tp) / (A)1.5;
+        A dal;
+        qp[k] = r * (A)R.cv * alpha_at<!is_dual<C>>(R, K, r, dal) * (K.T_w - tp) / (A)1.5;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -901,7 +970,7 @@ __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ r
         q = R.np > 0 ? q / (A)(double)R.np : (A)0.0;
         const A dT = K.T_w - K.T_sat;
         const A nu = (R.np > 0 && val(dT) != 0.0)
-                         ? q * (A)2.0 * (A)(double)R.cyl_r / ((A)R.rho_v * (A)R.cv * K.alpha * dT)
+                         ? q * (A)2.0 * (A)(double)R.cyl_r / ((A)R.rho_v * (A)R.cv * vapour_alpha(R, K) * dT)
                          : (A)0.0;
         R.acc[0] = mass;
         R.acc[1] = val(q);
@@ -992,82 +1061,104 @@ Variant variant_shape(int precision, int kernel, int v)
 }
 
 template <typename S, int TX, int TY, int NT>
-static hipError_t lbm_go(bool write_f, const RunDev *runs, const Tile *tiles, int n, int pf, int pt, int ph,
-                         long long step, hipStream_t st)
+static hipError_t lbm_go(bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf, int pt,
+                         int ph, long long step, hipStream_t st)
 {
-    if (write_f) k_lbm<S, TX, TY, NT, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
-    else k_lbm<S, TX, TY, NT, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    // phase-dependent properties are instantiated for FP32 and FP64 only
+    constexpr bool kPhase = std::is_same<S, float>::value || std::is_same<S, double>::value;
+    if constexpr (kPhase) {
+        if (phase) {
+            if (write_f) k_lbm<S, TX, TY, NT, true, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+            else k_lbm<S, TX, TY, NT, false, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+            return hipGetLastError();
+        }
+    } else {
+        if (phase) return hipErrorInvalidValue;
+    }
+    if (write_f) k_lbm<S, TX, TY, NT, true, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    else k_lbm<S, TX, TY, NT, false, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
     return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t lbm_impl(int v, bool write_f, const RunDev *runs, const Tile *tiles, int n, int pf, int pt, int ph,
-                           long long step, hipStream_t st)
+static hipError_t lbm_impl(int v, bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf,
+                           int pt, int ph, long long step, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     if constexpr (std::is_same<S, Dual>::value) {
         if (v != 0) return hipErrorInvalidValue;
-        return lbm_go<S, 16, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
     } else if constexpr (std::is_same<S, double>::value) {
         switch (v) {
-        case 0: return lbm_go<S, 32, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
-        case 1: return lbm_go<S, 16, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 1: return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (v) {
-        case 0: return lbm_go<S, 32, 16, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
-        case 1: return lbm_go<S, 64, 16, 512>(write_f, runs, tiles, n, pf, pt, ph, step, st);
-        case 2: return lbm_go<S, 32, 32, 512>(write_f, runs, tiles, n, pf, pt, ph, step, st);
-        case 3: return lbm_go<S, 32, 8, 256>(write_f, runs, tiles, n, pf, pt, ph, step, st);
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 1: return lbm_go<S, 64, 16, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 2: return lbm_go<S, 32, 32, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 3: return lbm_go<S, 32, 8, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
         default: return hipErrorInvalidValue;
         }
     }
 }
 
-hipError_t launch_lbm(int precision, int variant, bool write_f, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                      int pf, int pt, int ph, long long step, hipStream_t stream)
+hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, const RunDev *runs_dev, const Tile *tiles,
+                      int n_tiles, int pf, int pt, int ph, long long step, hipStream_t stream)
 {
     switch (precision) {
-    case 0: return lbm_impl<double>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 1: return lbm_impl<float>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 2: return lbm_impl<__half>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 4: return lbm_impl<Dual>(variant, write_f, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 0: return lbm_impl<double>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 1: return lbm_impl<float>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 2: return lbm_impl<__half>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 4: return lbm_impl<Dual>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename C, int TX, int TY, int NT>
-static hipError_t th_go(int rk, const RunDev *runs, const Tile *tiles, int n, int pt, long long step, hipStream_t st)
+static hipError_t th_go(int rk, bool phase, const RunDev *runs, const Tile *tiles, int n, int pt, long long step,
+                        hipStream_t st)
 {
-    if (rk == 4) k_thermal<C, TX, TY, 4, NT><<<n, NT, 0, st>>>(runs, tiles, pt, step);
-    else if (rk == 2) k_thermal<C, TX, TY, 2, NT><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+    if constexpr (!is_dual<C>) {
+        if (phase) {
+            if (rk == 4) k_thermal<C, TX, TY, 4, NT, true><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+            else if (rk == 2) k_thermal<C, TX, TY, 2, NT, true><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+            else return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+    } else {
+        if (phase) return hipErrorInvalidValue;
+    }
+    if (rk == 4) k_thermal<C, TX, TY, 4, NT, false><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+    else if (rk == 2) k_thermal<C, TX, TY, 2, NT, false><<<n, NT, 0, st>>>(runs, tiles, pt, step);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_thermal(int precision, int rk, int variant, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                          int pt, long long step, hipStream_t stream)
+hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
+                          int n_tiles, int pt, long long step, hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (precision == 4) {
         if (variant != 0) return hipErrorInvalidValue;
-        return th_go<Dual, 16, 8, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+        return th_go<Dual, 16, 8, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
     }
     if (precision == 0) {
         switch (variant) {
-        case 0: return th_go<double, 16, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-        case 1: return th_go<double, 32, 16, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+        case 0: return th_go<double, 16, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+        case 1: return th_go<double, 32, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
         default: return hipErrorInvalidValue;
         }
     }
     switch (variant) {
-    case 0: return th_go<float, 64, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 1: return th_go<float, 32, 32, 512>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 2: return th_go<float, 64, 32, 1024>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 3: return th_go<float, 32, 32, 256>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 4: return th_go<float, 64, 64, 1024>(rk, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 0: return th_go<float, 64, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 1: return th_go<float, 32, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 4: return th_go<float, 64, 64, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -29,6 +29,7 @@ _CONFIG_FIELDS = [
     ("rho_gref", C.c_double), ("rho_l", C.c_double), ("rho_v", C.c_double),
     ("rho_wall", C.c_double), ("u_in", C.c_double), ("alpha_T", C.c_double), ("cv", C.c_double),
     ("precision", C.c_int32), ("check_every", C.c_int32), ("rho_ref_shift", C.c_double),
+    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double),
 ]
 
 EXPORTED = [

@@ -55,7 +55,7 @@ def test_workspace_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=2), dict(ny=3), dict(bc_x=2), dict(precision=7), dict(rk_stages=3), dict(nu=0.0),
+    dict(nx=2), dict(ny=3), dict(bc_x=3), dict(precision=7), dict(rk_stages=3), dict(nu=0.0),
     dict(G=0.0), dict(cyl_r=30, cyl_x=20), dict(warmup_steps=-1),
 ])
 def test_invalid_configs_rejected(bad):

@@ -195,15 +195,16 @@ def test_fp32_error_after_1000_steps(lbm_mod):
 # after 1000 steps of a 256x128 channel (R 8, no warm-up) against the FP64 oracle.  Storage rounding
 # has relative spacing 2^-11 (FP16) or 2^-8 (BF16) on f_i - w_i rho_ref; with rho_ref = rho_l the
 # liquid's populations keep most of their bits, with rho_ref = 1 (f_i - w_i) they do not.  The bounds
-# are three times the errors measured on MI355X (rho, u, T: max-norm relative over fluid nodes, u
-# relative to max(|u|, u_in); Nu: relative).
+# are about three times the errors measured on MI355X (rho, u, T: max-norm relative over fluid nodes,
+# u relative to max(|u|, u_in)); Nu (relative) samples a thin layer at the wall and moves by a few
+# times between builds that only reorder FP32 operations, so its bound is about ten times.
 STORAGE_BOUNDS = {
     # (Re, precision, shift): (rho, u, T, Nu)
-    (30000.0, "f16", "rho_l"): (1.5e-3, 1.5e-2, 2e-3, 1e-4),
-    (30000.0, "f16", "one"): (4e-2, 2e-1, 4e-2, 2e-3),
-    (30000.0, "bf16", "rho_l"): (2e-2, 1.5e-1, 2.5e-2, 1.2e-2),
-    (300.0, "f16", "rho_l"): (7e-4, 6e-3, 6e-4, 1.2e-4),
-    (300.0, "bf16", "rho_l"): (2e-2, 1.2e-1, 1.5e-2, 1.5e-2),
+    (30000.0, "f16", "rho_l"): (1.5e-3, 1.5e-2, 2e-3, 3e-4),
+    (30000.0, "f16", "one"): (4e-2, 2e-1, 4e-2, 5e-3),
+    (30000.0, "bf16", "rho_l"): (2e-2, 1.5e-1, 2.5e-2, 2.5e-2),
+    (300.0, "f16", "rho_l"): (7e-4, 6e-3, 6e-4, 3e-4),
+    (300.0, "bf16", "rho_l"): (2e-2, 1.2e-1, 1.5e-2, 4e-2),
 }
 
 
