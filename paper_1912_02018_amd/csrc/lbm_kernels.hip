@@ -711,7 +711,7 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     };
 
     // right-hand side L(Y) of eq. energy at LDS position c with the coefficients of slot j
-    __device__ static C rhs(const Smem &sm, const Consts<C> &K, const Slots &S, int j, int c)
+    __device__ static C rhs(const Smem &sm, const Consts<C> &K, const Slots &S, int j, int c, bool phase)
     {
         // the 5x5 window read as positive offsets from its lowest corner
         const C *b = sm.Y + opaque_index(c - 2 * RW - 2);
@@ -738,8 +738,10 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
         const C s5 = ((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2));
         const C s8 = (a22 + b22) + (a2m2 + b2m2);
         C dg;
-        if constexpr (PH)
-            dg = S.al[j] * ((C)(2 * W2) * s2 + (C)(2 * W5) * s5 + (C)(2 * W8) * s8);
+        // (a run without phase-dependent properties takes the same arithmetic in either launch, so
+        // batching it with runs that have them does not change its result)
+        if (PH && phase)
+            dg = S.al[PH ? j : 0] * ((C)(2 * W2) * s2 + (C)(2 * W5) * s5 + (C)(2 * W8) * s8);
         else
             dg = K.alpha2w2 * s2 + K.alpha2w5 * s5 + K.alpha2w8 * s8;
         const C gdx = (C)W2 * (d.d11 + d.d1m) + (C)W5 * ((C)2 * (d.d21 + d.d2m) + d.d12 + d.d1m2) +
@@ -753,7 +755,7 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
 
     // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input
     template <int s>
-    __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S)
+    __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S, bool phase)
     {
         constexpr int CNT = G::count(s);
         C kv[ITER];
@@ -762,7 +764,7 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
             kv[j] = 0;
             const int r = threadIdx.x + NT * j;
             if (r >= CNT || S.ev[j] < 0) continue;
-            kv[j] = rhs(sm, K, S, j, S.ev[j]);
+            kv[j] = rhs(sm, K, S, j, S.ev[j], phase);
         }
         if constexpr (s < NS) __syncthreads();  // every stage input has been read
 #pragma unroll
@@ -887,11 +889,12 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         S.c0[j] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
     }
 
-    Th::template stage<1>(sm, K, S);
-    Th::template stage<2>(sm, K, S);
+    const bool phase = PH && R.phase_props;
+    Th::template stage<1>(sm, K, S, phase);
+    Th::template stage<2>(sm, K, S, phase);
     if constexpr (NS == 4) {
-        Th::template stage<3>(sm, K, S);
-        Th::template stage<4>(sm, K, S);
+        Th::template stage<3>(sm, K, S, phase);
+        Th::template stage<4>(sm, K, S, phase);
     }
 
     // the tile's slots come first
