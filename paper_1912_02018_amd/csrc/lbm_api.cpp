@@ -989,20 +989,26 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
     HIPCHK(h, hipEventCreate(&e1));
     for (int k = 0; k < 2; ++k) {
         if (k == 1 && h->rk == 0) continue;
-        float best_ms = 1e30f;
+        // two interleaved rounds over the variants; each keeps its faster round
+        const int nv = lbm::variant_count(h->precision, k);
+        std::vector<float> t(nv, 1e30f);
+        for (int round = 0; round < 2; ++round)
+            for (int v = 0; v < nv; ++v) {
+                int rc = lbm_set_variant(h, k, v);
+                if (rc) return rc;
+                if ((rc = lbm_time_kernel(h, k, 3))) return rc;
+                HIPCHK(h, hipEventRecord(e0, h->stream));
+                if ((rc = lbm_time_kernel(h, k, launches))) return rc;
+                HIPCHK(h, hipEventRecord(e1, h->stream));
+                HIPCHK(h, hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+                t[v] = std::min(t[v], ms);
+            }
         int best_v = h->var[k];
-        for (int v = 0; v < lbm::variant_count(h->precision, k); ++v) {
-            int rc = lbm_set_variant(h, k, v);
-            if (rc) return rc;
-            if ((rc = lbm_time_kernel(h, k, 3))) return rc;
-            HIPCHK(h, hipEventRecord(e0, h->stream));
-            if ((rc = lbm_time_kernel(h, k, launches))) return rc;
-            HIPCHK(h, hipEventRecord(e1, h->stream));
-            HIPCHK(h, hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) { best_ms = ms; best_v = v; }
-        }
+        float best_ms = 1e30f;
+        for (int v = 0; v < nv; ++v)
+            if (t[v] < best_ms) { best_ms = t[v]; best_v = v; }
         int rc = lbm_set_variant(h, k, best_v);
         if (rc) return rc;
         if (best) best[k] = best_v;

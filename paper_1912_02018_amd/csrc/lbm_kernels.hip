@@ -473,8 +473,9 @@ template <int RW, typename C> __device__ inline PairD<C> pair_diffs(const C *s, 
 // ------------------------------------------------------------------------------------------
 // k_lbm: streaming + moments + psi + force + central-moment collision
 // ------------------------------------------------------------------------------------------
-template <typename S, int TX, int TY, int NT, bool WRITE_F, bool PH>
-__global__ __launch_bounds__(NT) void k_lbm(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pf,
+// OCC > 0: ask the compiler for at least OCC waves per SIMD (a register budget)
+template <typename S, int TX, int TY, int NT, bool WRITE_F, bool PH, int OCC = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void k_lbm(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pf,
                                             int pt, int ph, long long step)
 {
     using C = CT<S>;
@@ -700,12 +701,11 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
         int own[ITER];  // LDS position of the slot
         int ev[ITER];   // LDS position the operator is evaluated at; < 0: value held (solid, inlet ghost)
         C T0[ITER], acc[ITER];
-        // L(Y) = sum over the axis pairs (+-1, 0), (+-2, 0), (0, +-1), (0, +-2) of cS * (sum of the
-        // pair) + cd * (difference of the pair), + 2 alpha w_k (sum of the pair) over the diagonal
-        // pairs, + gx, gy times the diagonal part of the isotropic gradient, + c0 Y + c2 sqrt(Y):
-        // the Laplacian, the density-gradient term, the upwind convection and the source with the
-        // slot's own coefficients folded in
-        C cS10[ITER], cS20[ITER], cd10[ITER], cd20[ITER], cS01[ITER], cS02[ITER], cd01[ITER], cd02[ITER];
+        // coefficients of L(Y) at the slot (8 registers, which keeps the occupancy of tiles with
+        // many slots per thread): u/12, v/12 and |u| c_d, |v| c_d of the upwind convection, the
+        // density-gradient coefficients gx, gy, the centre coefficient c0 (the Laplacian's and the
+        // convection's centre weights and the linear part c1 of the source) and c2 of sqrt(Y)
+        C u12[ITER], v12[ITER], au[ITER], av[ITER];
         C gx[ITER], gy[ITER], c0[ITER], c2[ITER];
         C al[PH ? ITER : 1];  // alpha at the slot (phase-dependent properties)
     };
@@ -731,8 +731,12 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
         d.d11 = a11 - b11; d.d1m = a1m - b1m; d.d21 = a21 - b21; d.d2m = a2m - b2m;
         d.d12 = a12 - b12; d.d1m2 = a1m2 - b1m2; d.d22 = a22 - b22; d.d2m2 = a2m2 - b2m2;
         // axis pairs: Laplacian, upwind convection and the axis part of the gradient term
-        const C ax = S.cS10[j] * S10 + S.cS20[j] * S20 + S.cd10[j] * d.d10 + S.cd20[j] * d.d20 + S.cS01[j] * S01 +
-                     S.cS02[j] * S02 + S.cd01[j] * d.d01 + S.cd02[j] * d.d02;
+        const C a = (PH && phase) ? S.al[PH ? j : 0] : K.alpha;
+        const C ax = (C)(2 * W1) * a * (S10 + S01) + (C)(2 * W4) * a * (S20 + S02) -
+                     (S.u12[j] * ((C)8 * d.d10 - d.d20) + S.au[j] * (S20 - (C)4 * S10) +
+                      S.v12[j] * ((C)8 * d.d01 - d.d02) + S.av[j] * (S02 - (C)4 * S01)) +
+                     S.gx[j] * ((C)W1 * d.d10 + (C)(2 * W4) * d.d20) +
+                     S.gy[j] * ((C)W1 * d.d01 + (C)(2 * W4) * d.d02);
         // diagonal pairs: Laplacian (2 alpha w_k) and the diagonal part of the gradient term
         const C s2 = (a11 + b11) + (a1m + b1m);
         const C s5 = ((a21 + b21) + (a2m + b2m)) + ((a12 + b12) + (a1m2 + b1m2));
@@ -838,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         S.own[j] = 0; S.ev[j] = -1;
         S.T0[j] = S.acc[j] = S.gx[j] = S.gy[j] = S.c0[j] = S.c2[j] = 0;
         if constexpr (PH) S.al[j] = 0;
-        S.cS10[j] = S.cS20[j] = S.cd10[j] = S.cd20[j] = S.cS01[j] = S.cS02[j] = S.cd01[j] = S.cd02[j] = 0;
+        S.u12[j] = S.v12[j] = S.au[j] = S.av[j] = 0;
         const int r = threadIdx.x + NT * j;
         if (r >= NSLOT) continue;
         const int p = kSlots<TX, TY, NS>.pos[r];
@@ -876,16 +880,11 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         const C u12 = u * (C)(1.0 / 12.0), v12 = v * (C)(1.0 / 12.0);
         S.gx[j] = gx;
         S.gy[j] = gy;
-        const C a2w1 = (C)(2 * W1) * al, a2w4 = (C)(2 * W4) * al;
         if constexpr (PH) S.al[j] = al;
-        S.cS10[j] = a2w1 + (C)4 * au;
-        S.cS20[j] = a2w4 - au;
-        S.cd10[j] = (C)W1 * gx - (C)8 * u12;
-        S.cd20[j] = (C)(2 * W4) * gx + u12;
-        S.cS01[j] = a2w1 + (C)4 * av;
-        S.cS02[j] = a2w4 - av;
-        S.cd01[j] = (C)W1 * gy - (C)8 * v12;
-        S.cd02[j] = (C)(2 * W4) * gy + v12;
+        S.u12[j] = u12;
+        S.v12[j] = v12;
+        S.au[j] = au;
+        S.av[j] = av;
         S.c0[j] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
     }
 
@@ -1038,10 +1037,10 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // Launch variants (tile shape, threads per block) and launchers
 // ------------------------------------------------------------------------------------------
 // stream+collide: FP32 and reduced-precision storage / FP64
-static const Variant kLbm32[] = {{32, 16, 256}, {64, 16, 512}, {32, 32, 512}, {32, 8, 256}};
+static const Variant kLbm32[] = {{32, 16, 256}, {64, 16, 512}, {32, 32, 512}, {32, 8, 256}, {32, 8, 256}};
 static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
-static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}, {64, 64, 1024}};
+static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}};
 static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
 // tangent precision (40-byte values): one small tile each (the RK4 temperature tile with its
 // 8-node halo stays within the 160 KB of LDS)
@@ -1051,8 +1050,8 @@ static const Variant kTanTh[] = {{16, 8, 256}};
 int variant_count(int precision, int kernel)
 {
     if (precision == 4) return 1;
-    if (kernel == 0) return precision == 0 ? 2 : 4;
-    return precision == 0 ? 2 : 5;
+    if (kernel == 0) return precision == 0 ? 2 : 5;
+    return precision == 0 ? 2 : 4;
 }
 
 Variant variant_shape(int precision, int kernel, int v)
@@ -1063,7 +1062,7 @@ Variant variant_shape(int precision, int kernel, int v)
     return precision == 0 ? kTh64[v] : kTh32[v];
 }
 
-template <typename S, int TX, int TY, int NT>
+template <typename S, int TX, int TY, int NT, int OCC = 0>
 static hipError_t lbm_go(bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf, int pt,
                          int ph, long long step, hipStream_t st)
 {
@@ -1071,15 +1070,15 @@ static hipError_t lbm_go(bool write_f, bool phase, const RunDev *runs, const Til
     constexpr bool kPhase = std::is_same<S, float>::value || std::is_same<S, double>::value;
     if constexpr (kPhase) {
         if (phase) {
-            if (write_f) k_lbm<S, TX, TY, NT, true, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
-            else k_lbm<S, TX, TY, NT, false, true><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+            if (write_f) k_lbm<S, TX, TY, NT, true, true, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+            else k_lbm<S, TX, TY, NT, false, true, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
             return hipGetLastError();
         }
     } else {
         if (phase) return hipErrorInvalidValue;
     }
-    if (write_f) k_lbm<S, TX, TY, NT, true, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
-    else k_lbm<S, TX, TY, NT, false, false><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    if (write_f) k_lbm<S, TX, TY, NT, true, false, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    else k_lbm<S, TX, TY, NT, false, false, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
     return hipGetLastError();
 }
 
@@ -1103,6 +1102,7 @@ static hipError_t lbm_impl(int v, bool write_f, bool phase, const RunDev *runs, 
         case 1: return lbm_go<S, 64, 16, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
         case 2: return lbm_go<S, 32, 32, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
         case 3: return lbm_go<S, 32, 8, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 4: return lbm_go<S, 32, 8, 256, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1161,7 +1161,6 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
     case 1: return th_go<float, 32, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
     case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
     case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 4: return th_go<float, 64, 64, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
     default: return hipErrorInvalidValue;
     }
 }
