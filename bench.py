@@ -219,12 +219,20 @@ def sensitivity_run(lbm, steps=4000, average_from=2000):
 
 def hbm_resident_run(lbm, steps=200):
     """The Re 300 channel scaled by 8 (8192x4096, cylinder R 256 at x 2048): a state of ~3 GB that
-    no cache holds.  Coupled steps from the initial liquid state (no physical warm-up; the same
-    per-step work)."""
+    no cache holds, with FP32 populations and with FP16 storage (shift w_i rho_l).  Coupled steps
+    from the initial liquid state (no physical warm-up; the same per-step work)."""
+    out = _hbm_resident(lbm, PREC["f32"], steps)
+    out["f16_store"] = _hbm_resident(lbm, PREC["f16s"], steps)
+    return out
+
+
+def _hbm_resident(lbm, prec, steps):
     import torch
     from paper_1912_02018_amd.config import cylinder_config
-    cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=PREC["f32"],
+    cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=prec,
                           warmup=0)
+    if prec >= 2:
+        cfg = cfg.replace(rho_ref_shift=lbm.saturation(cfg)["rho_l"])
     sim = lbm.Simulation(cfg)
     sim.step(10)
     sim.autotune(5)
@@ -240,9 +248,10 @@ def hbm_resident_run(lbm, steps=200):
         e1.record(sim.stream)
         torch.cuda.synchronize()
         kt[KERNEL_NAMES[k]] = e0.elapsed_time(e1) / 20
-    rec = {"workload": "boiling-cylinder-8192x4096-R256-Re300-rk4-f32", "nodes": nodes, "mlups": round(mlups, 1),
+    pname = {v: k for k, v in PREC.items()}[prec]
+    rec = {"workload": f"boiling-cylinder-8192x4096-R256-Re300-rk4-{pname}", "nodes": nodes, "mlups": round(mlups, 1),
            "ms_per_step": round(ms / steps, 4), "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
-           "kernel_hbm_gbs": {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, PREC["f32"]) * nodes / (kt[KERNEL_NAMES[k]] * 1e-3) / 1e9, 1)
+           "kernel_hbm_gbs": {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (kt[KERNEL_NAMES[k]] * 1e-3) / 1e9, 1)
                               for k in (0, 1)},
            "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}}
     sim.close()
