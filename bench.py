@@ -285,8 +285,7 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
         kt[k] = e0.elapsed_time(e1) / launches  # ms per launch
     dom = max(kt, key=kt.get)
     name = KERNEL_NAMES[dom]
-    tx, ty, nt = sim.variants(dom)[sim.get_variant(dom)][:3]
-    variant = f"{name}<{tx}x{ty}x{nt}>" if dom == 0 else f"{name}<{tx}x{ty}x{nt},rk{cfg.rk_stages}>"
+    variant = variant_name(dom, sim.variants(dom)[sim.get_variant(dom)], cfg.rk_stages)
     if dom == 0:
         per_launch = kernel_bytes_per_lup(0, prec) * nodes
         achieved = per_launch / (kt[dom] * 1e-3) / 1e9
@@ -303,6 +302,16 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
     roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
                               for k, v in kt.items()}
     return roof
+
+
+def variant_name(kernel: int, shape, rk: int) -> str:
+    """Name of a launch variant, as the profile summaries key it: k_lbm<tx x ty x threads[,wN]>,
+    k_thermal<tx x ty x threads,rkS> (wN: register budget for N waves per SIMD)."""
+    tx, ty, nt, mw = shape
+    budget = f",w{mw}" if mw else ""
+    if kernel == 0:
+        return f"k_lbm<{tx}x{ty}x{nt}{budget}>"
+    return f"k_thermal<{tx}x{ty}x{nt}{budget},rk{rk}>"
 
 
 def base_line(args, prec, value, ms_step, workload_cfg):

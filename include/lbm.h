@@ -179,12 +179,13 @@ enum { LBM_KERNEL_STREAM_COLLIDE = 0, LBM_KERNEL_THERMAL = 1 };
 int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
 
 /* Launch variants of the stencil kernels (kernel 0: k_lbm, 1: k_thermal): each is a tile of
- * tx x ty nodes per workgroup of `threads` threads.  lbm_set_variant rebuilds the tile tables
+ * tx x ty nodes per workgroup of `threads` threads, compiled with a register budget for min_waves
+ * waves per SIMD if min_waves > 0 (any output pointer may be NULL).  lbm_set_variant rebuilds the tile tables
  * (waits for the stream); lbm_autotune times every variant of both kernels on the handle's
  * current state with HIP events (`launches` launches each) and keeps the fastest, writing the
  * chosen indices to best[2] if not NULL. */
 int lbm_variant_count(int precision, int kernel);
-int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads);
+int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads, int *min_waves);
 int lbm_set_variant(lbm_handle *h, int kernel, int variant);
 int lbm_get_variant(const lbm_handle *h, int kernel);
 int lbm_autotune(lbm_handle *h, int launches, int *best);

@@ -952,13 +952,14 @@ int lbm_variant_count(int precision, int kernel)
     return lbm::variant_count(precision, kernel);
 }
 
-int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads)
+int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads, int *min_waves)
 {
     const lbm::Variant v = lbm::variant_shape(precision, kernel, variant);
     if (v.tx == 0) return LBM_EINVAL;
     if (tx) *tx = v.tx;
     if (ty) *ty = v.ty;
     if (threads) *threads = v.nt;
+    if (min_waves) *min_waves = v.min_waves;
     return LBM_OK;
 }
 

@@ -60,6 +60,7 @@ struct Tile {
 // Launch variant of a stencil kernel: tile of tx x ty nodes per workgroup of nt threads.
 struct Variant {
     int tx, ty, nt;
+    int min_waves;  // > 0: compiled with a register budget for this many waves per SIMD
 };
 
 // kernel: 0 = stream+collide (k_lbm), 1 = temperature update (k_thermal)

@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // Launch variants (tile shape, threads per block) and launchers
 // ------------------------------------------------------------------------------------------
 // stream+collide: FP32 and reduced-precision storage / FP64
-static const Variant kLbm32[] = {{32, 16, 256}, {64, 16, 512}, {32, 32, 512}, {32, 8, 256}, {32, 8, 256}};
+static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 512, 0}, {32, 8, 256, 0}, {32, 8, 256, 6}};
 static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
 static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}};
@@ -1056,7 +1056,7 @@ int variant_count(int precision, int kernel)
 
 Variant variant_shape(int precision, int kernel, int v)
 {
-    if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0};
+    if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0, 0};
     if (precision == 4) return kernel == 0 ? kTanLbm[v] : kTanTh[v];
     if (kernel == 0) return precision == 0 ? kLbm64[v] : kLbm32[v];
     return precision == 0 ? kTh64[v] : kTh32[v];

@@ -85,7 +85,7 @@ def load_library():
     L.lbm_time_kernel.argtypes = [vp, i32, i32]
     ip = C.POINTER(C.c_int)
     L.lbm_variant_count.argtypes = [i32, i32]
-    L.lbm_variant_shape.argtypes = [i32, i32, i32, ip, ip, ip]
+    L.lbm_variant_shape.argtypes = [i32, i32, i32, ip, ip, ip, ip]
     L.lbm_set_variant.argtypes = [vp, i32, i32]
     L.lbm_get_variant.argtypes = [vp, i32]
     L.lbm_autotune.argtypes = [vp, i32, ip]
@@ -188,13 +188,14 @@ class Simulation:
         self._check(self._L.lbm_time_kernel(self.h, int(kernel), int(n)))
 
     def variants(self, kernel: int):
-        """(tx, ty, threads) of every launch variant of a kernel (0 k_lbm, 1 k_thermal)."""
+        """(tx, ty, threads, min_waves) of every launch variant of a kernel (0 k_lbm, 1 k_thermal);
+        min_waves > 0: compiled with a register budget for that many waves per SIMD."""
         prec = self.cfgs[0].precision
         out = []
         for v in range(self._L.lbm_variant_count(prec, kernel)):
-            a, b, c = C.c_int(), C.c_int(), C.c_int()
-            self._L.lbm_variant_shape(prec, kernel, v, C.byref(a), C.byref(b), C.byref(c))
-            out.append((a.value, b.value, c.value))
+            a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+            self._L.lbm_variant_shape(prec, kernel, v, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
+            out.append((a.value, b.value, c.value, d.value))
         return out
 
     def set_variant(self, kernel: int, variant: int):
