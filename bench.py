@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--skip-physical-warmup", action="store_true",
                     help="start coupled steps at once (short profiler runs; same per-step work)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variants")
+    ap.add_argument("--variants", default=None, metavar="L,T",
+                    help="launch variant indices of k_lbm and k_thermal (instead of autotuning)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep"],
                     help="c2: 1024x512 boiling channel (default); c3: the same at Re 30000; sweep: 64 uneven runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -147,7 +149,7 @@ def sweep_summary(args, lbm):
     stepped one after another (shorter timing than --workload sweep)."""
     from paper_1912_02018_amd.config import sweep_configs
     sub = argparse.Namespace(**vars(args))
-    sub.steps, sub.warmup, sub.kernel_launches = 1000, 100, 20
+    sub.steps, sub.warmup, sub.kernel_launches, sub.variants = 1000, 100, 20, None
     rec = run_sweep(sub, lbm, sweep_configs(64, 2018, PREC["f32"]), PREC["f32"])
     return {"workload": rec["config"]["workload"], "nodes": rec["config"]["nodes"], "mlups": rec["value"],
             "sequential_mlups": rec["sequential_mlups"], "ratio": rec["batched_over_sequential"],
@@ -240,14 +242,7 @@ def _hbm_resident(lbm, prec, steps):
     ms, _ = timed_steps(torch, sim, steps)
     nodes = cfg.nx * cfg.ny
     mlups = nodes / (ms / steps * 1e-3) / 1e6
-    kt = {}
-    for k in (0, 1):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        sim.time_kernel(k, 20)
-        e1.record(sim.stream)
-        torch.cuda.synchronize()
-        kt[KERNEL_NAMES[k]] = e0.elapsed_time(e1) / 20
+    kt = dict(zip(KERNEL_NAMES.values(), sim.profile_steps(20)))  # in-step dispatch durations
     pname = {v: k for k, v in PREC.items()}[prec]
     rec = {"workload": f"boiling-cylinder-8192x4096-R256-Re300-rk4-{pname}", "nodes": nodes, "mlups": round(mlups, 1),
            "ms_per_step": round(ms / steps, 4), "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
@@ -256,6 +251,15 @@ def _hbm_resident(lbm, prec, steps):
            "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}}
     sim.close()
     return rec
+
+
+def choose_variants(args, sim, launches):
+    """Given variants (--variants), the defaults (--no-autotune) or the autotuner's choice."""
+    if args.variants:
+        for k, v in enumerate(int(x) for x in args.variants.split(",")):
+            sim.set_variant(k, v)
+    elif not args.no_autotune:
+        sim.autotune(launches)
 
 
 def timed_steps(torch, sim, steps):
@@ -270,9 +274,9 @@ def timed_steps(torch, sim, steps):
     return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
-def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
-    """Average duration of isolated launches of each kernel of the step (HIP events on the
-    library's stream) and the roofline of the dominant one."""
+def isolated_kernel_ms(torch, sim, launches):
+    """Average duration of back-to-back launches of each kernel on an unchanging state (HIP events
+    on the library's stream): the inputs stay cache-hot, so these run faster than in the step."""
     kt = {}
     for k in (0, 1):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -283,6 +287,14 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
         e1.record(sim.stream)
         torch.cuda.synchronize()
         kt[k] = e0.elapsed_time(e1) / launches  # ms per launch
+    return kt
+
+
+def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
+    """Average duration of each kernel inside the running step sequence (`launches` further steps
+    right after the timed region, every k_lbm / k_thermal dispatch timed by the start / stop HIP
+    events of the dispatch itself) and the roofline of the dominant one."""
+    kt = dict(enumerate(sim.profile_steps(launches)))
     dom = max(kt, key=kt.get)
     name = KERNEL_NAMES[dom]
     variant = variant_name(dom, sim.variants(dom)[sim.get_variant(dom)], cfg.rk_stages)
@@ -299,6 +311,8 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload):
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(variant, workload)}
     roof["kernel"] = variant
     roof["kernel_ms"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in kt.items()}
+    roof["timing"] = f"in-step: {launches} steps after the timed region, dispatch events per kernel"
+    roof["kernel_ms_isolated"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in isolated_kernel_ms(torch, sim, launches).items()}
     roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
                               for k, v in kt.items()}
     return roof
@@ -336,8 +350,7 @@ def run_single(args, lbm, cfg, prec, workload, re):
     import torch
     sim = lbm.Simulation(cfg)
     sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
-    if not args.no_autotune:
-        sim.autotune(20)                # launch variants timed on the coupled state (untimed)
+    choose_variants(args, sim, 20)      # launch variants timed on the coupled state (untimed)
     sim.step(args.warmup)
     ms, wall = timed_steps(torch, sim, args.steps)
     ms_step = ms / args.steps
@@ -352,7 +365,8 @@ def run_single(args, lbm, cfg, prec, workload, re):
         "workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r, "u_in": cfg.u_in, "Re": re,
         "rk_stages": cfg.rk_stages, "warmup_steps_untimed": cfg.warmup_steps + args.warmup,
         "parallelism": "single-gpu",
-        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}})
+        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]},
+        "variants": [sim.get_variant(0), sim.get_variant(1)]})
     line["roofline"] = kernel_roofline(torch, sim, cfg, prec, nodes, args.kernel_launches, workload)
     line["wall_s"] = round(wall, 3)
     line["diagnostics"] = {"mass": mass, "q_mean": q, "nu": nu}
@@ -368,8 +382,7 @@ def run_sweep(args, lbm, cfgs, prec):
     nodes = sum(c.nx * c.ny for c in cfgs)
     sim = lbm.Simulation(cfgs)
     sim.step(max(c.warmup_steps for c in cfgs))
-    if not args.no_autotune:
-        sim.autotune(10)
+    choose_variants(args, sim, 10)
     sim.step(args.warmup)
     ms, wall = timed_steps(torch, sim, args.steps)
     ms_step = ms / args.steps
@@ -389,7 +402,8 @@ def run_sweep(args, lbm, cfgs, prec):
         "workload": f"boiling-sweep-{len(cfgs)}-runs", "runs": len(cfgs), "nodes": nodes,
         "grids": "64*{4..16} x half, R 8..32, superheat 0.02..0.30 Tc, Re 30..3000 (seed 2018)",
         "parallelism": "single-gpu",
-        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}})
+        "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]},
+        "variants": [sim.get_variant(0), sim.get_variant(1)]})
     line["sequential_mlups"] = round(sequential, 1)
     line["batched_over_sequential"] = round(batched / sequential, 3)
     line["roofline"] = kernel_roofline(torch, sim, cfgs[0], prec, nodes, max(10, args.kernel_launches // 10),

@@ -190,6 +190,16 @@ int lbm_set_variant(lbm_handle *h, int kernel, int variant);
 int lbm_get_variant(const lbm_handle *h, int kernel);
 int lbm_autotune(lbm_handle *h, int launches, int *best);
 
+/* Advances every run by n_steps steps (1 <= n_steps <= LBM_MAX_PROFILE_STEPS), launching each
+ * step directly (no graph replay) with the stream-and-collide and temperature kernels timed by
+ * start / stop events of their own dispatches, so the durations are those inside the running
+ * step sequence (caches as a step leaves them), not of repeated isolated launches.  Writes the
+ * mean milliseconds per dispatch to kernel_ms[0] (k_lbm) and kernel_ms[1] (k_thermal; 0 if no
+ * step advanced the temperature).  Synchronises the stream.  The state advances exactly as with
+ * lbm_step.  Errors: LBM_EINVAL (NULL handle or kernel_ms, count out of range), LBM_EDEVICE. */
+#define LBM_MAX_PROFILE_STEPS 4096
+int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms);
+
 /* Options.  LBM_OPT_GRAPHS (default 1): lbm_step captures one period of its launch pattern
  * (2 steps, or the least common multiple with diag_every / check_every) into a HIP graph once
  * every run is past its warm-up, and replays it; 0 launches every kernel directly. */

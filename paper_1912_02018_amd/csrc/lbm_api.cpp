@@ -624,11 +624,12 @@ static int set_fields_impl(lbm_handle *h, int run, const double *rho, const doub
     return LBM_OK;
 }
 
-// Enqueue the launches of one step (no host synchronisation).
-static int enqueue_step(lbm_handle *h)
+// Enqueue the launches of one step (no host synchronisation).  tm (optional, two entries): events
+// of the k_lbm and the k_thermal dispatch; *thermal_ran tells whether the second was launched.
+static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *thermal_ran = nullptr)
 {
     HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
-                              h->step, h->stream));
+                              h->step, h->stream, tm));
     bool thermal = false;
     for (int r = 0; r < h->n_runs; ++r) {
         const lbm_config &k = h->cfgs[r];
@@ -640,9 +641,10 @@ static int enqueue_step(lbm_handle *h)
     }
     if (thermal) {
         HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
-                                      h->stream));
+                                      h->stream, tm ? tm + 1 : nullptr));
         h->pt ^= 1;
     }
+    if (thermal_ran) *thermal_ran = thermal;
     h->pf ^= 1;
     h->ph ^= 1;
     h->step += 1;
@@ -944,6 +946,53 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
         return LBM_OK;
     }
     return fail(h, LBM_EINVAL, "unknown kernel %d", kernel);
+}
+
+namespace {
+// events of a profiled step sequence, released on every return path
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms)
+{
+    if (!h) return LBM_EINVAL;
+    if (!kernel_ms) return fail(h, LBM_EINVAL, "kernel_ms is NULL");
+    if (n_steps < 1 || n_steps > LBM_MAX_PROFILE_STEPS)
+        return fail(h, LBM_EINVAL, "profiled step count %d outside [1, %d]", n_steps, LBM_MAX_PROFILE_STEPS);
+    EventPool pool;
+    pool.ev.reserve((size_t)4 * n_steps);
+    for (int k = 0; k < 4 * n_steps; ++k) {
+        hipEvent_t e;
+        HIPCHK(h, hipEventCreate(&e));
+        pool.ev.push_back(e);
+    }
+    std::vector<char> ran((size_t)n_steps, 0);
+    for (int s = 0; s < n_steps; ++s) {
+        const lbm::Timing tm[2] = {{pool.ev[4 * s], pool.ev[4 * s + 1]}, {pool.ev[4 * s + 2], pool.ev[4 * s + 3]}};
+        bool th = false;
+        const int rc = enqueue_step(h, tm, &th);
+        if (rc) return rc;
+        ran[s] = th;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double sum[2] = {0, 0};
+    int cnt[2] = {0, 0};
+    for (int s = 0; s < n_steps; ++s)
+        for (int k = 0; k < 2; ++k) {
+            if (k == 1 && !ran[s]) continue;
+            float ms = 0;
+            HIPCHK(h, hipEventElapsedTime(&ms, pool.ev[4 * s + 2 * k], pool.ev[4 * s + 2 * k + 1]));
+            sum[k] += ms;
+            cnt[k] += 1;
+        }
+    for (int k = 0; k < 2; ++k) kernel_ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+    return LBM_OK;
 }
 
 int lbm_variant_count(int precision, int kernel)

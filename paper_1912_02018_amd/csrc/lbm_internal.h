@@ -67,14 +67,21 @@ struct Variant {
 int variant_count(int precision, int kernel);
 Variant variant_shape(int precision, int kernel, int v);
 
+// Start / stop events filled in by a kernel's own dispatch (timing inside the step sequence).
+struct Timing {
+    hipEvent_t start, stop;
+};
+
 // Launchers (each enqueues on `stream`; returns a hipError_t).
 hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream);
 // phase: some run of the launch has phase-dependent transport or a heated wall (FP32 / FP64
-// only); the kernels without these features are launched otherwise
+// only); the kernels without these features are launched otherwise.  timing (optional): events
+// that take the start and end timestamps of this dispatch.
 hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, const RunDev *runs_dev, const Tile *tiles,
-                      int n_tiles, int parity_f, int parity_t, int parity_h, long long step, hipStream_t stream);
+                      int n_tiles, int parity_f, int parity_t, int parity_h, long long step, hipStream_t stream,
+                      const Timing *timing = nullptr);
 hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
-                          int n_tiles, int parity_t, long long step, hipStream_t stream);
+                          int n_tiles, int parity_t, long long step, hipStream_t stream, const Timing *timing = nullptr);
 hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int parity_t, int accumulate,
                        hipStream_t stream);
 

@@ -20,6 +20,7 @@
 #include "lbm_internal.h"
 
 #include <hip/hip_bf16.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 #include <type_traits>
@@ -1037,7 +1038,8 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // Launch variants (tile shape, threads per block) and launchers
 // ------------------------------------------------------------------------------------------
 // stream+collide: FP32 and reduced-precision storage / FP64
-static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 512, 0}, {32, 8, 256, 0}, {32, 8, 256, 6}};
+static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 512, 0}, {32, 8, 256, 0},
+                                 {32, 8, 256, 6},  {64, 8, 512, 6},  {64, 8, 512, 7}};
 static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
 static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}};
@@ -1050,7 +1052,7 @@ static const Variant kTanTh[] = {{16, 8, 256}};
 int variant_count(int precision, int kernel)
 {
     if (precision == 4) return 1;
-    if (kernel == 0) return precision == 0 ? 2 : 5;
+    if (kernel == 0) return precision == 0 ? 2 : 7;
     return precision == 0 ? 2 : 4;
 }
 
@@ -1062,105 +1064,116 @@ Variant variant_shape(int precision, int kernel, int v)
     return precision == 0 ? kTh64[v] : kTh32[v];
 }
 
+// Launch of a stencil kernel; with `tm`, through hipExtLaunchKernelGGL, whose start / stop events
+// take the timestamps of the kernel's own dispatch (its duration inside the step sequence)
+template <typename... P, typename... A>
+static void dispatch(void (*kern)(P...), int grid, int block, hipStream_t st, const Timing *tm, A... args)
+{
+    if (tm) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, tm->start, tm->stop, 0, static_cast<P>(args)...);
+    else hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, static_cast<P>(args)...);
+}
+
 template <typename S, int TX, int TY, int NT, int OCC = 0>
 static hipError_t lbm_go(bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf, int pt,
-                         int ph, long long step, hipStream_t st)
+                         int ph, long long step, hipStream_t st, const Timing *tm)
 {
     // phase-dependent properties are instantiated for FP32 and FP64 only
     constexpr bool kPhase = std::is_same<S, float>::value || std::is_same<S, double>::value;
     if constexpr (kPhase) {
         if (phase) {
-            if (write_f) k_lbm<S, TX, TY, NT, true, true, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
-            else k_lbm<S, TX, TY, NT, false, true, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+            if (write_f) dispatch(k_lbm<S, TX, TY, NT, true, true, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+            else dispatch(k_lbm<S, TX, TY, NT, false, true, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
             return hipGetLastError();
         }
     } else {
         if (phase) return hipErrorInvalidValue;
     }
-    if (write_f) k_lbm<S, TX, TY, NT, true, false, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
-    else k_lbm<S, TX, TY, NT, false, false, OCC><<<n, NT, 0, st>>>(runs, tiles, pf, pt, ph, step);
+    if (write_f) dispatch(k_lbm<S, TX, TY, NT, true, false, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+    else dispatch(k_lbm<S, TX, TY, NT, false, false, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
     return hipGetLastError();
 }
 
 template <typename S>
 static hipError_t lbm_impl(int v, bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf,
-                           int pt, int ph, long long step, hipStream_t st)
+                           int pt, int ph, long long step, hipStream_t st, const Timing *tm)
 {
     if (n <= 0) return hipSuccess;
     if constexpr (std::is_same<S, Dual>::value) {
         if (v != 0) return hipErrorInvalidValue;
-        return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
     } else if constexpr (std::is_same<S, double>::value) {
         switch (v) {
-        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
-        case 1: return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 1: return lbm_go<S, 16, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (v) {
-        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
-        case 1: return lbm_go<S, 64, 16, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
-        case 2: return lbm_go<S, 32, 32, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
-        case 3: return lbm_go<S, 32, 8, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
-        case 4: return lbm_go<S, 32, 8, 256, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st);
+        case 0: return lbm_go<S, 32, 16, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 1: return lbm_go<S, 64, 16, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 2: return lbm_go<S, 32, 32, 512>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 3: return lbm_go<S, 32, 8, 256>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 4: return lbm_go<S, 32, 8, 256, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 5: return lbm_go<S, 64, 8, 512, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 6: return lbm_go<S, 64, 8, 512, 7>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
         default: return hipErrorInvalidValue;
         }
     }
 }
 
 hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, const RunDev *runs_dev, const Tile *tiles,
-                      int n_tiles, int pf, int pt, int ph, long long step, hipStream_t stream)
+                      int n_tiles, int pf, int pt, int ph, long long step, hipStream_t stream, const Timing *timing)
 {
     switch (precision) {
-    case 0: return lbm_impl<double>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 1: return lbm_impl<float>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 2: return lbm_impl<__half>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
-    case 4: return lbm_impl<Dual>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream);
+    case 0: return lbm_impl<double>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, timing);
+    case 1: return lbm_impl<float>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, timing);
+    case 2: return lbm_impl<__half>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, timing);
+    case 3: return lbm_impl<__hip_bfloat16>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, timing);
+    case 4: return lbm_impl<Dual>(variant, write_f, phase, runs_dev, tiles, n_tiles, pf, pt, ph, step, stream, timing);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename C, int TX, int TY, int NT>
 static hipError_t th_go(int rk, bool phase, const RunDev *runs, const Tile *tiles, int n, int pt, long long step,
-                        hipStream_t st)
+                        hipStream_t st, const Timing *tm)
 {
     if constexpr (!is_dual<C>) {
         if (phase) {
-            if (rk == 4) k_thermal<C, TX, TY, 4, NT, true><<<n, NT, 0, st>>>(runs, tiles, pt, step);
-            else if (rk == 2) k_thermal<C, TX, TY, 2, NT, true><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+            if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, true>, n, NT, st, tm, runs, tiles, pt, step);
+            else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, true>, n, NT, st, tm, runs, tiles, pt, step);
             else return hipErrorInvalidValue;
             return hipGetLastError();
         }
     } else {
         if (phase) return hipErrorInvalidValue;
     }
-    if (rk == 4) k_thermal<C, TX, TY, 4, NT, false><<<n, NT, 0, st>>>(runs, tiles, pt, step);
-    else if (rk == 2) k_thermal<C, TX, TY, 2, NT, false><<<n, NT, 0, st>>>(runs, tiles, pt, step);
+    if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
+    else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
-                          int n_tiles, int pt, long long step, hipStream_t stream)
+                          int n_tiles, int pt, long long step, hipStream_t stream, const Timing *timing)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (precision == 4) {
         if (variant != 0) return hipErrorInvalidValue;
-        return th_go<Dual, 16, 8, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+        return th_go<Dual, 16, 8, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     }
     if (precision == 0) {
         switch (variant) {
-        case 0: return th_go<double, 16, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
-        case 1: return th_go<double, 32, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+        case 0: return th_go<double, 16, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+        case 1: return th_go<double, 32, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
         default: return hipErrorInvalidValue;
         }
     }
     switch (variant) {
-    case 0: return th_go<float, 64, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 1: return th_go<float, 32, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
-    case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream);
+    case 0: return th_go<float, 64, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 1: return th_go<float, 32, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     default: return hipErrorInvalidValue;
     }
 }

@@ -37,7 +37,7 @@ EXPORTED = [
     "lbm_get_state", "lbm_set_state", "lbm_wall_heat_flux", "lbm_total_mass", "lbm_derived",
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
-    "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation",
+    "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation", "lbm_profile_steps",
 ]
 OPT_GRAPHS = 0
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
@@ -90,6 +90,7 @@ def load_library():
     L.lbm_get_variant.argtypes = [vp, i32]
     L.lbm_autotune.argtypes = [vp, i32, ip]
     L.lbm_set_option.argtypes = [vp, i32, i32]
+    L.lbm_profile_steps.argtypes = [vp, i32, dp]
     L.lbm_step_count.argtypes = [vp]
     L.lbm_step_count.restype = i64
     L.lbm_last_error.argtypes = [vp]
@@ -186,6 +187,13 @@ class Simulation:
     def time_kernel(self, kernel: int, n: int):
         """Enqueue n launches of one kernel of the step without advancing the state."""
         self._check(self._L.lbm_time_kernel(self.h, int(kernel), int(n)))
+
+    def profile_steps(self, n: int):
+        """Advance n steps with each k_lbm / k_thermal dispatch timed by its own start / stop
+        events; returns their mean durations in ms (k_lbm, k_thermal)."""
+        out = (C.c_double * 2)()
+        self._check(self._L.lbm_profile_steps(self.h, int(n), out))
+        return out[0], out[1]
 
     def variants(self, kernel: int):
         """(tx, ty, threads, min_waves) of every launch variant of a kernel (0 k_lbm, 1 k_thermal);

@@ -254,6 +254,23 @@ def test_graph_replay_matches_eager_bitwise(lbm_mod):
     assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
 
 
+def test_profiled_steps_advance_like_steps(lbm_mod):
+    """lbm_profile_steps advances the state exactly as lbm_step (bit for bit) and reports a
+    positive mean duration for both kernels; out-of-range counts are rejected."""
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32)
+    a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
+    a.step(10)
+    b.step(10)
+    ms = a.profile_steps(37)
+    b.step(37)
+    assert a.step_count == b.step_count == 47
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
+    assert 0 < ms[0] < 100 and 0 < ms[1] < 100, ms
+    for bad in (0, 4097):
+        with pytest.raises(lbm_mod.LBMError):
+            a.profile_steps(bad)
+
+
 @pytest.mark.parametrize("precision", [FP32, FP64])
 def test_launch_variants_agree(lbm_mod, precision):
     """Every tile shape of both stencil kernels gives the same state bit for bit (the per-node
