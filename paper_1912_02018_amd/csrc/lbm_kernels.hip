@@ -817,17 +817,61 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
     }
     const Consts<C> K(R);
 
+    // LDS positions of this thread's slots, fetched from the constant table first so that their
+    // latency overlaps the field loads
+    int spos[ITER];
+#pragma unroll
+    for (int j = 0; j < ITER; ++j) {
+        const int r = threadIdx.x + NT * j;
+        spos[j] = r < NSLOT ? (int)kSlots<TX, TY, NS>.pos[r] : 0;
+    }
+
     // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
-    for (int n = threadIdx.x; n < RX * RH; n += NT) {
-        const int lx = n % RX, ly = n / RX, p = ly * RW + lx;
-        int rx, ry;
-        const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
-        const unsigned idx = (unsigned)(ry * P + rx);
-        const bool wall = PH && kind == WALL_GHOST;
-        sm.rho[p] = wall ? K.rho_w : ld_at<C>(R.rho, idx);
-        sm.ux[p] = wall ? (C)0 : ld_at<C>(R.ux, idx);
-        sm.uy[p] = wall ? (C)0 : ld_at<C>(R.uy, idx);
-        sm.Y[p] = kind == INLET_GHOST ? K.T_sat : (wall ? K.T_w : ld_at<C>(R.T[pt], idx));
+    if constexpr (is_dual<C>) {
+        // (40-byte values: one position at a time keeps the registers of the tangent kernel low)
+        for (int n = threadIdx.x; n < RX * RH; n += NT) {
+            const int lx = n % RX, ly = n / RX, p = ly * RW + lx;
+            int rx, ry;
+            const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+            const unsigned idx = (unsigned)(ry * P + rx);
+            sm.rho[p] = ld_at<C>(R.rho, idx);
+            sm.ux[p] = ld_at<C>(R.ux, idx);
+            sm.uy[p] = ld_at<C>(R.uy, idx);
+            sm.Y[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
+        }
+    } else {
+        // every position of the thread: all loads are issued before the first LDS write (one memory
+        // round trip); ghost positions map to valid nodes, so every load is in bounds, and the
+        // ghost values replace the loaded ones afterwards
+        constexpr int IL = (RX * RH + NT - 1) / NT;
+        C lr[IL], lu[IL], lv[IL], lt[IL];
+        unsigned inlet = 0, wall = 0;
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            const int n = min(threadIdx.x + NT * i, RX * RH - 1);
+            const int lx = n % RX, ly = n / RX;
+            int rx, ry;
+            const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+            const unsigned idx = (unsigned)(ry * P + rx);
+            if (kind == INLET_GHOST) inlet |= 1u << i;
+            if (PH && kind == WALL_GHOST) wall |= 1u << i;
+            lr[i] = ld_at<C>(R.rho, idx);
+            lu[i] = ld_at<C>(R.ux, idx);
+            lv[i] = ld_at<C>(R.uy, idx);
+            lt[i] = ld_at<C>(R.T[pt], idx);
+        }
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            // (a thread past the region rewrites the last position with the value loaded for it,
+            // so that no load is sunk behind a branch)
+            const int n = min(threadIdx.x + NT * i, RX * RH - 1);
+            const int p = (n / RX) * RW + n % RX;
+            const bool w = (wall >> i) & 1u;
+            sm.rho[p] = w ? K.rho_w : lr[i];
+            sm.ux[p] = w ? (C)0 : lu[i];
+            sm.uy[p] = w ? (C)0 : lv[i];
+            sm.Y[p] = ((inlet >> i) & 1u) ? K.T_sat : (w ? K.T_w : lt[i]);
+        }
     }
     __syncthreads();
 
@@ -846,7 +890,7 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         S.u12[j] = S.v12[j] = S.au[j] = S.av[j] = 0;
         const int r = threadIdx.x + NT * j;
         if (r >= NSLOT) continue;
-        const int p = kSlots<TX, TY, NS>.pos[r];
+        const int p = spos[j];
         const int lx = p % RW, ly = p / RW;
         int rx, ry;
         const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
