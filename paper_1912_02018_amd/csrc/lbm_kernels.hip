@@ -363,7 +363,9 @@ __device__ inline bool near_cylinder(const RunDev &R, int x, int y)
 //   v in (0,1) q < 1/2 with a fluid node at x + c_i:  f_i = v f*_o(x) + (1 - v) f*_o(x + c_i), v = 2q
 //   v > 2      q < 1/2 without one:                    f_i = f*_o(x)
 //   v <= -1    q >= 1/2:                              f_i = f*_o(x)/(2q) + (2q - 1)/(2q) f*_i(x), v = -2q
-// The box keeps one node clear of every domain edge, so no neighbour index wraps.
+// f*_o(x + c_i) is the plain pull of direction o = opp(i): the box keeps one node clear of every
+// domain edge, so that pull is neither wrapped nor clamped, and only the wall fractions and the
+// node's own populations are loaded.
 template <typename S, typename C>
 __device__ inline void fix_near(const RunDev &R, const Consts<C> &K, const char *fin, int x, int y, C f[9])
 {
@@ -376,7 +378,7 @@ __device__ inline void fix_near(const RunDev &R, const Consts<C> &K, const char 
     for (int i = 1; i < 9; ++i) {
         v[i] = qt[i - 1];
         own[i] = ldf<S, C>(fin, plane, P, i, x, y, K);
-        nb[i] = ldf<S, C>(fin, plane, P, opp_of(i), x + cx_of(i), y + cy_of(i), K);
+        nb[i] = f[opp_of(i)];
     }
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
