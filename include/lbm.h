@@ -182,8 +182,11 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
  * tx x ty nodes per workgroup of `threads` threads, compiled with a register budget for min_waves
  * waves per SIMD if min_waves > 0 (any output pointer may be NULL).  lbm_set_variant rebuilds the tile tables
  * (waits for the stream); lbm_autotune times every variant of both kernels on the handle's
- * current state with HIP events (`launches` launches each) and keeps the fastest, writing the
- * chosen indices to best[2] if not NULL. */
+ * current state with HIP events (`launches` launches each, 20 if 0) and keeps the fastest, writing
+ * the chosen indices to best[2] if not NULL.  Every tuning is remembered for the rest of the process
+ * per device and workload shape (precision, RK stages, heated-wall / phase-property launch, and each
+ * run's nx, ny, cylinder radius and x boundary); launches < 0 takes the remembered choice for the
+ * handle's shape without timing anything, and tunes with 20 launches when there is none. */
 int lbm_variant_count(int precision, int kernel);
 int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, int *threads, int *min_waves);
 int lbm_set_variant(lbm_handle *h, int kernel, int variant);

@@ -12,7 +12,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 using lbm::RunDev;
@@ -948,6 +951,8 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
     return fail(h, LBM_EINVAL, "unknown kernel %d", kernel);
 }
 
+}  // extern "C"
+
 namespace {
 // events of a profiled step sequence, released on every return path
 struct EventPool {
@@ -958,6 +963,8 @@ struct EventPool {
     }
 };
 }  // namespace
+
+extern "C" {
 
 int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms)
 {
@@ -1030,9 +1037,48 @@ int lbm_get_variant(const lbm_handle *h, int kernel)
     return h->var[kernel];
 }
 
+}  // extern "C"
+
+namespace {
+// Tuned launch variants of this process, per device and workload shape: precision, RK stages, the
+// extended-feature launch, and every run's grid, cylinder radius and x boundary.
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string tune_key(const lbm_handle *h)
+{
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::string k = std::to_string(dev) + "/" + std::to_string(h->precision) + "/" + std::to_string(h->rk) + "/" +
+                    std::to_string(h->phase ? 1 : 0);
+    for (const auto &c : h->cfgs)
+        k += "/" + std::to_string(c.nx) + "x" + std::to_string(c.ny) + "r" + std::to_string(c.cyl_r) + "b" +
+             std::to_string(c.bc_x);
+    return k;
+}
+}  // namespace
+
+extern "C" {
+
 int lbm_autotune(lbm_handle *h, int launches, int *best)
 {
     if (!h) return LBM_EINVAL;
+    const std::string key = tune_key(h);
+    if (launches < 0) {
+        std::pair<int, int> hit(-1, -1);
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) hit = it->second;
+        }
+        if (hit.first >= 0) {
+            int rc = lbm_set_variant(h, 0, hit.first);
+            if (!rc && h->rk != 0) rc = lbm_set_variant(h, 1, hit.second);
+            if (rc) return rc;
+            if (best) { best[0] = h->var[0]; best[1] = h->var[1]; }
+            return LBM_OK;
+        }
+    }
     if (launches <= 0) launches = 20;
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
@@ -1065,6 +1111,9 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (best && h->rk == 0) best[1] = h->var[1];
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = std::make_pair(h->var[0], h->var[1]);
     return LBM_OK;
 }
 

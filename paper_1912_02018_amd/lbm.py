@@ -212,10 +212,11 @@ class Simulation:
     def get_variant(self, kernel: int) -> int:
         return int(self._L.lbm_get_variant(self.h, int(kernel)))
 
-    def autotune(self, launches: int = 20):
-        """Time every launch variant of both kernels on the current state; keep the fastest."""
+    def autotune(self, launches: int = 20, cached: bool = False):
+        """Time every launch variant of both kernels on the current state; keep the fastest.
+        cached: reuse this process's earlier choice for the same workload shape, if any."""
         best = (C.c_int * 2)()
-        self._check(self._L.lbm_autotune(self.h, int(launches), best))
+        self._check(self._L.lbm_autotune(self.h, -1 if cached else int(launches), best))
         return best[0], best[1]
 
     def set_graphs(self, enabled: bool):

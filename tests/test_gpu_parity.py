@@ -296,6 +296,22 @@ def test_launch_variants_agree(lbm_mod, precision):
                 assert all(np.array_equal(x, y) for x, y in zip(st, ref_state)), (vl, vt)
 
 
+def test_autotune_cache(lbm_mod):
+    """A tuned choice is remembered per workload shape: cached=True on another handle of the same
+    shape applies it without timing; a new shape is tuned on its first cached call."""
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32)
+    a = lbm_mod.Simulation(cfg)
+    best = a.autotune(3)
+    b = lbm_mod.Simulation(cfg)
+    b.set_variant(0, (best[0] + 1) % len(b.variants(0)))
+    assert b.autotune(cached=True) == best
+    assert (b.get_variant(0), b.get_variant(1)) == best
+    c = lbm_mod.Simulation(cfg.replace(nx=112))
+    got = c.autotune(cached=True)
+    assert 0 <= got[0] < len(c.variants(0)) and 0 <= got[1] < len(c.variants(1))
+    assert c.autotune(cached=True) == got
+
+
 def test_autotune_keeps_results(lbm_mod):
     cfg = cylinder_case(nx=128, ny=64, precision=FP32)
     a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
