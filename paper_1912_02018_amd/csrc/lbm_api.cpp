@@ -1080,9 +1080,13 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
         }
     }
     if (launches <= 0) launches = 20;
-    hipEvent_t e0, e1;
-    HIPCHK(h, hipEventCreate(&e0));
-    HIPCHK(h, hipEventCreate(&e1));
+    EventPool pool;  // released on every return path
+    for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        HIPCHK(h, hipEventCreate(&e));
+        pool.ev.push_back(e);
+    }
+    hipEvent_t e0 = pool.ev[0], e1 = pool.ev[1];
     for (int k = 0; k < 2; ++k) {
         if (k == 1 && h->rk == 0) continue;
         // two interleaved rounds over the variants; each keeps its faster round
@@ -1109,8 +1113,6 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
         if (rc) return rc;
         if (best) best[k] = best_v;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (best && h->rk == 0) best[1] = h->var[1];
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune_cache[key] = std::make_pair(h->var[0], h->var[1]);
