@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--skip-physical-warmup", action="store_true",
                     help="start coupled steps at once (short profiler runs; same per-step work)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variants")
+    ap.add_argument("--stream-groups", type=int, default=3,
+                    help="sweep: runs stepped as this many contiguous groups on streams of their own")
     ap.add_argument("--variants", default=None, metavar="L,T",
                     help="launch variant indices of k_lbm and k_thermal (instead of autotuning)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep"],
@@ -407,6 +409,8 @@ def run_sweep(args, lbm, cfgs, prec):
     sim = lbm.Simulation(cfgs)
     sim.step(max(c.warmup_steps for c in cfgs))
     choose_variants(args, sim, 10)
+    groups = max(1, min(args.stream_groups, len(cfgs)))
+    sim.set_stream_groups(groups)
     sim.step(args.warmup)
     ms, wall = timed_steps(torch, sim, args.steps)
     ms_step = ms / args.steps
@@ -425,6 +429,7 @@ def run_sweep(args, lbm, cfgs, prec):
     line = base_line(args, prec, batched, ms_step, {
         "workload": f"boiling-sweep-{len(cfgs)}-runs", "runs": len(cfgs), "nodes": nodes,
         "grids": "64*{4..16} x half, R 8..32, superheat 0.02..0.30 Tc, Re 30..3000 (seed 2018)",
+        "stream_groups": groups,
         "parallelism": "single-gpu",
         "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]},
         "variants": [sim.get_variant(0), sim.get_variant(1)]})

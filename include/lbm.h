@@ -206,8 +206,20 @@ int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms);
 /* Options.  LBM_OPT_GRAPHS (default 1): lbm_step captures one period of its launch pattern
  * (2 steps, or the least common multiple with diag_every / check_every) into a HIP graph once
  * every run is past its warm-up, and replays it; 0 launches every kernel directly. */
-enum { LBM_OPT_GRAPHS = 0 };
+enum { LBM_OPT_GRAPHS = 0, LBM_OPT_STREAM_GROUPS = 1 };
 int lbm_set_option(lbm_handle *h, int option, int value);
+
+/* LBM_OPT_STREAM_GROUPS (default 1): with G > 1 (1 <= G <= min(LBM_MAX_STREAM_GROUPS, n_runs)),
+ * lbm_step splits the runs into G contiguous ranges of about equal node counts and steps each range
+ * on a private stream of its own (default priority), forked from and joined back to the handle's
+ * stream by events, so that one range's temperature update runs beside another range's streaming.
+ * Launches are then direct (no graph replay).  Each run sees the same launches in the same order as
+ * with one stream, so results are bitwise the same.  Setting the option waits for the handle's
+ * stream.  lbm_get_option returns the current value (-1 for an unknown option or a NULL handle);
+ * lbm_stream_group_runs gives the runs [run0, run1) of group `group` (LBM_EINVAL if out of range). */
+#define LBM_MAX_STREAM_GROUPS 8
+int lbm_get_option(const lbm_handle *h, int option);
+int lbm_stream_group_runs(const lbm_handle *h, int group, int *run0, int *run1);
 
 /* Steps taken since creation / the last set_fields / set_state. */
 int64_t lbm_step_count(const lbm_handle *h);

@@ -47,6 +47,15 @@ struct lbm_handle {
     long long step = 0;
     bool use_graphs = true;
     std::vector<StepGraph> graphs;
+    // stream groups (LBM_OPT_STREAM_GROUPS > 1): contiguous ranges of runs stepped on streams of their
+    // own, so that one group's temperature update overlaps another group's streaming
+    struct Group {
+        int run0, run1;          // runs [run0, run1)
+        hipStream_t s;
+        hipEvent_t done;
+    };
+    std::vector<Group> groups;
+    hipEvent_t fork = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     std::string err;
 };
@@ -654,6 +663,49 @@ static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *th
     return LBM_OK;
 }
 
+// One step of every run, group by group on the groups' streams (same launches and order per run
+// as enqueue_step; the tiles of a group's runs are contiguous in the tile tables).
+static int enqueue_step_groups(lbm_handle *h)
+{
+    bool thermal = false;
+    for (int r = 0; r < h->n_runs; ++r)
+        thermal |= h->step >= h->cfgs[r].warmup_steps && h->cfgs[r].rk_stages > 0;
+    for (const auto &g : h->groups) {
+        const int l0 = h->lbm_off[g.run0], l1 = h->lbm_off[g.run1 - 1] + h->lbm_cnt[g.run1 - 1];
+        HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm + l0, l1 - l0, h->pf,
+                                  h->pt, h->ph, h->step, g.s));
+        for (int r = g.run0; r < g.run1; ++r) {
+            const lbm_config &k = h->cfgs[r];
+            const bool fon = h->step >= k.warmup_steps;
+            const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
+            const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
+            if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, g.s));
+        }
+        if (thermal) {
+            const int t0 = h->th_off[g.run0], t1 = h->th_off[g.run1 - 1] + h->th_cnt[g.run1 - 1];
+            HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th + t0, t1 - t0,
+                                          h->pt, h->step, g.s));
+        }
+    }
+    if (thermal) h->pt ^= 1;
+    h->pf ^= 1;
+    h->ph ^= 1;
+    h->step += 1;
+    return LBM_OK;
+}
+
+static void drop_groups(lbm_handle *h)
+{
+    for (auto &g : h->groups) {
+        (void)hipStreamSynchronize(g.s);
+        (void)hipEventDestroy(g.done);
+        (void)hipStreamDestroy(g.s);
+    }
+    h->groups.clear();
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    h->fork = nullptr;
+}
+
 static long long lcm_ll(long long a, long long b)
 {
     long long x = a, y = b;
@@ -686,6 +738,20 @@ int lbm_step(lbm_handle *h, int n_steps)
     }
     const long long L = pattern_length(h);
     long long remaining = n_steps;
+    if (!h->groups.empty() && n_steps > 0) {
+        // fork from the caller's stream, step every group on its own stream, join back
+        HIPCHK(h, hipEventRecord(h->fork, h->stream));
+        for (const auto &g : h->groups) HIPCHK(h, hipStreamWaitEvent(g.s, h->fork, 0));
+        for (long long k = 0; k < remaining; ++k) {
+            int rc = enqueue_step_groups(h);
+            if (rc) return rc;
+        }
+        for (const auto &g : h->groups) {
+            HIPCHK(h, hipEventRecord(g.done, g.s));
+            HIPCHK(h, hipStreamWaitEvent(h->stream, g.done, 0));
+        }
+        remaining = 0;
+    }
     while (remaining > 0) {
         // replay a captured window when the pattern repeats (all runs past warm-up, window aligned)
         const bool periodic = h->step >= max_warm;
@@ -1127,7 +1193,61 @@ int lbm_set_option(lbm_handle *h, int option, int value)
         drop_graphs(h);
         return LBM_OK;
     }
+    if (option == LBM_OPT_STREAM_GROUPS) {
+        if (value < 1 || value > LBM_MAX_STREAM_GROUPS || value > h->n_runs)
+            return fail(h, LBM_EINVAL, "stream groups %d outside [1, min(%d, runs = %d)]", value, LBM_MAX_STREAM_GROUPS,
+                        h->n_runs);
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        drop_groups(h);
+        if (value == 1) return LBM_OK;
+        // contiguous ranges of runs with about equal node counts
+        std::vector<double> cum(h->n_runs + 1, 0.0);
+        for (int r = 0; r < h->n_runs; ++r) cum[r + 1] = cum[r] + (double)h->cfgs[r].nx * h->cfgs[r].ny;
+        int r0 = 0;
+        for (int g = 0; g < value; ++g) {
+            int r1 = r0 + 1;
+            const double target = cum[h->n_runs] * (g + 1) / value;
+            while (r1 < h->n_runs - (value - 1 - g) && cum[r1] + 0.5 * (cum[r1 + 1] - cum[r1]) < target) ++r1;
+            if (g == value - 1) r1 = h->n_runs;
+            lbm_handle::Group grp{r0, r1, nullptr, nullptr};
+            hipError_t e = hipStreamCreateWithFlags(&grp.s, hipStreamNonBlocking);
+            if (e == hipSuccess) {
+                e = hipEventCreateWithFlags(&grp.done, hipEventDisableTiming);
+                if (e != hipSuccess) (void)hipStreamDestroy(grp.s);
+            }
+            if (e != hipSuccess) {
+                drop_groups(h);
+                return fail(h, LBM_EDEVICE, "stream group: %s", hipGetErrorString(e));
+            }
+            h->groups.push_back(grp);
+            r0 = r1;
+        }
+        hipError_t e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            drop_groups(h);
+            return fail(h, LBM_EDEVICE, "stream group: %s", hipGetErrorString(e));
+        }
+        return LBM_OK;
+    }
     return fail(h, LBM_EINVAL, "unknown option %d", option);
+}
+
+int lbm_get_option(const lbm_handle *h, int option)
+{
+    if (!h) return -1;
+    if (option == LBM_OPT_GRAPHS) return h->use_graphs ? 1 : 0;
+    if (option == LBM_OPT_STREAM_GROUPS) return h->groups.empty() ? 1 : (int)h->groups.size();
+    return -1;
+}
+
+int lbm_stream_group_runs(const lbm_handle *h, int group, int *run0, int *run1)
+{
+    if (!h) return LBM_EINVAL;
+    const int n = h->groups.empty() ? 1 : (int)h->groups.size();
+    if (group < 0 || group >= n) return LBM_EINVAL;
+    if (run0) *run0 = h->groups.empty() ? 0 : h->groups[group].run0;
+    if (run1) *run1 = h->groups.empty() ? h->n_runs : h->groups[group].run1;
+    return LBM_OK;
 }
 
 int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
@@ -1139,6 +1259,7 @@ void lbm_destroy(lbm_handle *h)
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
+    drop_groups(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }

@@ -38,8 +38,9 @@ EXPORTED = [
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
     "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation", "lbm_profile_steps",
+    "lbm_get_option", "lbm_stream_group_runs",
 ]
-OPT_GRAPHS = 0
+OPT_GRAPHS, OPT_STREAM_GROUPS = 0, 1
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
 
 
@@ -90,6 +91,8 @@ def load_library():
     L.lbm_get_variant.argtypes = [vp, i32]
     L.lbm_autotune.argtypes = [vp, i32, ip]
     L.lbm_set_option.argtypes = [vp, i32, i32]
+    L.lbm_get_option.argtypes = [vp, i32]
+    L.lbm_stream_group_runs.argtypes = [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_profile_steps.argtypes = [vp, i32, dp]
     L.lbm_step_count.argtypes = [vp]
     L.lbm_step_count.restype = i64
@@ -221,6 +224,19 @@ class Simulation:
 
     def set_graphs(self, enabled: bool):
         self._check(self._L.lbm_set_option(self.h, OPT_GRAPHS, 1 if enabled else 0))
+
+    def set_stream_groups(self, groups: int):
+        """Step the runs as `groups` contiguous ranges on streams of their own (1: one stream)."""
+        self._check(self._L.lbm_set_option(self.h, OPT_STREAM_GROUPS, int(groups)))
+
+    def stream_groups(self):
+        """[(run0, run1), ...] of the current stream groups."""
+        out = []
+        for g in range(self._L.lbm_get_option(self.h, OPT_STREAM_GROUPS)):
+            a, b = C.c_int(), C.c_int()
+            self._check(self._L.lbm_stream_group_runs(self.h, g, C.byref(a), C.byref(b)))
+            out.append((a.value, b.value))
+        return out
 
     def set_fields(self, rho, ux, uy, T=None, run: int = 0):
         shp = self._shape(run)

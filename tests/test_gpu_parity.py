@@ -346,6 +346,37 @@ def test_degenerate_cases(lbm_mod):
     assert np.isfinite(q)
 
 
+def test_stream_groups_bitwise(lbm_mod):
+    """Runs stepped as stream groups (contiguous ranges of runs on streams of their own) end in the
+    same states, fields and heat fluxes as the same handle on one stream, through warm-ups that end at
+    different steps, heat-flux accumulation and NaN checks; out-of-range group counts are rejected."""
+    cfgs = [cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32, warmup_steps=30),
+            cylinder_case(nx=130, ny=70, r=8, cx=40, precision=FP32, dTr_wall=0.2, upwind_kind=1),
+            cylinder_case(nx=64, ny=40, r=5, cx=20, precision=FP32, warmup_steps=55, check_every=25),
+            cylinder_case(nx=160, ny=64, r=6, cx=40, precision=FP32, diag_every=7),
+            cylinder_case(nx=80, ny=48, r=6, cx=25, precision=FP32)]
+    ref = lbm_mod.Simulation(cfgs)
+    ref.step(61)
+    ref.step(89)
+    for groups in (2, 3, 5):
+        sim = lbm_mod.Simulation(cfgs)
+        sim.set_stream_groups(groups)
+        parts = sim.stream_groups()
+        assert len(parts) == groups and parts[0][0] == 0 and parts[-1][1] == len(cfgs)
+        assert all(a < b for a, b in parts) and all(parts[i][1] == parts[i + 1][0] for i in range(groups - 1))
+        sim.step(61)
+        sim.step(89)
+        for r in range(len(cfgs)):
+            assert all(np.array_equal(x, y) for x, y in zip(sim.get_state(r)[:3], ref.get_state(r)[:3])), (groups, r)
+            assert sim.wall_heat_flux(r) == ref.wall_heat_flux(r), (groups, r)
+        for bad in (0, 6, 9):
+            with pytest.raises(lbm_mod.LBMError):
+                sim.set_stream_groups(bad)
+        sim.set_stream_groups(1)
+        assert sim.stream_groups() == [(0, len(cfgs))]
+        sim.close()
+
+
 def test_batched_runs_equal_single_runs_bitwise(lbm_mod):
     """Runs stepped together in one handle (one launch per kernel over all their tiles) end in
     bit-identical states to the same runs stepped alone: tiles never mix runs and a run's arithmetic
