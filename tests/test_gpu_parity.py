@@ -180,6 +180,82 @@ def test_full_size_one_step(lbm_mod, precision, tol, tol_u):
             tol=tol, tol_u=tol_u, u_ref=cfg.u_in)
 
 
+def storage_half_ulp(v, pname):
+    """Half the spacing of the 16-bit storage format at |v| (FP16: 10 fraction bits, subnormal below
+    2^-14; BF16: 7 fraction bits)."""
+    a = np.abs(v)
+    if pname == "f16":
+        e = np.floor(np.log2(np.maximum(a, 2.0 ** -14)))
+        return 0.5 * 2.0 ** (e - 10)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -126)))
+    return 0.5 * 2.0 ** (e - 7)
+
+
+@pytest.mark.parametrize("pname", ["f16", "bf16"])
+def test_full_size_reduced_storage_one_step(lbm_mod, pname):
+    """1024x512 channel at Re 30000 (u_in 0.05) with the populations stored in FP16 / BF16 as
+    f - w_i rho_l: after 200 coupled steps on the GPU the oracle takes the GPU state (values the storage
+    represents) and both advance one step.
+      * every stored population differs from the oracle's by at most half a storage ulp of
+        f - w_i rho_l plus the FP32 rounding of the step;
+      * T (advanced with rho, u of the step, computed in FP32 from the shared state) to FP32 rounding;
+      * rho, u of the new state (a macroscopic pass over the stored populations) against the oracle
+        reading the same GPU state, to FP32 rounding."""
+    from paper_1912_02018_amd.config import FP16S, BF16S, config3
+    prec = FP16S if pname == "f16" else BF16S
+    rl, rv = coex()
+    cfg = config3(prec).replace(warmup_steps=0, rho_l=rl, rho_v=rv, rho_ref_shift=rl)
+    sim = developed_state(lbm_mod, cfg, 200)
+    fs, hist, T, step = sim.get_state()
+    ref = oracle.Sim(cfg.replace(precision=FP64))
+    ref.set_state(fs, hist, T, step)
+    sim.step(1)
+    ref.step(1)
+    fluid = ref.fields()["mask"] == 0
+    fg, hg, Tg, sg = sim.get_state()
+    fo, _, To, _ = ref.get_state()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    worst = 0.0
+    for i in range(9):
+        shift = float(np.float32(w[i] * rl))
+        bound = storage_half_ulp(fo[i] - shift, pname) + 4e-6 * np.abs(fo[i][fluid]).max()
+        worst = max(worst, float((np.abs(fg[i] - fo[i]) / bound)[fluid].max()))
+    errT = rel(Tg[fluid], To[fluid])
+    print(f"[parity] {pname} storage 1024x512 one step: f* at most {worst:.3f} of half a storage ulp + FP32, "
+          f"T {errT:.2e}", flush=True)
+    assert worst <= 1.0
+    assert errT <= 2e-6
+    now = oracle.Sim(cfg.replace(precision=FP64))
+    now.set_state(fg, hg, Tg, sg)
+    compare(sim, now, f"{pname} storage 1024x512 macroscopic pass of the stepped GPU state", tol=2e-6, tol_u=2e-5,
+            u_ref=cfg.u_in)
+
+
+def test_full_size_sweep_sampled_runs(lbm_mod):
+    """The 64-run sweep at its full sizes (14.9 M nodes) in the bench's launch configuration (one
+    handle, autotuned variants, 3 stream groups): after 100 steps three sampled runs (the largest,
+    the smallest and one between) are handed to the oracle and both advance one step (FP32 vs FP64)."""
+    from paper_1912_02018_amd.config import sweep_configs
+    cfgs = [c.replace(warmup_steps=0) for c in sweep_configs(64, 2018, FP32)]
+    sizes = [c.nx * c.ny for c in cfgs]
+    picks = [int(np.argmax(sizes)), int(np.argmin(sizes)), len(cfgs) // 2]
+    sim = lbm_mod.Simulation(cfgs)
+    sim.step(10)
+    sim.autotune(3)
+    sim.set_stream_groups(3)
+    sim.step(90)
+    refs = {}
+    for r in picks:
+        fs, hist, T, step = sim.get_state(r)
+        refs[r] = oracle.Sim(cfgs[r].replace(precision=FP64))
+        refs[r].set_state(fs, hist, T, step)
+    sim.step(1)
+    for r in picks:
+        refs[r].step(1)
+        compare(sim, refs[r], f"sweep run {r} ({cfgs[r].nx}x{cfgs[r].ny}) one step from the batched GPU state",
+                tol=2e-6, tol_u=2e-5, u_ref=cfgs[r].u_in, run=r)
+
+
 def test_fp32_error_after_1000_steps(lbm_mod):
     """FP32 path against the FP64 oracle on the heated cylinder after 1000 steps."""
     cfg64 = cylinder_case()

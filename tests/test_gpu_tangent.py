@@ -131,6 +131,42 @@ def test_tangent_vs_oracle_central_differences(mods, tangent):
     check_gradient(g, fd, J, th, "oracle-fd")
 
 
+def test_full_size_tangent_vs_oracle(mods):
+    """The sensitivity workload at its full size (512x256, R 16, Re 300, superheat 0.1 T_c, no
+    warm-up; Nu accumulated every step): J = mean Nu of the states 50..99 and dJ/dtheta from one
+    tangent run, against the FP64 oracle's J and its central differences (8 perturbed oracle runs)."""
+    from paper_1912_02018_amd.config import config5
+    _, sens = mods
+    steps, avg_from = 100, 50
+    base = config5(FP64).replace(rho_l=_C["rho_l"], rho_v=_C["rho_v"], diag_every=1)
+    J, g = sens.nu_average_and_gradient(base, steps, avg_from)
+
+    def oracle_J_of(cfg):
+        sim = oracle.Sim(cfg)
+        tot, n = 0.0, 0
+        for step in range(steps):
+            if step >= avg_from:
+                tot += sim.wall_heat_flux()[1]
+                n += 1
+            sim.step(1)
+        return tot / n
+
+    J0 = oracle_J_of(base)
+    print(f"full size J gpu {J:.14e} oracle {J0:.14e}", flush=True)
+    assert abs(J - J0) <= 1e-11 * abs(J0)
+    th = sens.params_of(base)
+    hs = REL_H * scales(th)
+    Js = []
+    for k in range(4):
+        for sgn in (1.0, -1.0):
+            t = th.copy()
+            t[k] += sgn * hs[k]
+            Js.append(oracle_J_of(sens.with_params(base, t)))
+    Js = np.array(Js)
+    fd = (Js[0::2] - Js[1::2]) / (2 * hs)
+    check_gradient(g, fd, J, th, "full-size oracle-fd")
+
+
 def test_autograd_function(mods, tangent):
     import torch
     _, sens = mods
