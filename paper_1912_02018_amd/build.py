@@ -29,5 +29,24 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+C_EXAMPLE_SRC = os.path.join(ROOT, "tests", "c_abi_example.c")
+C_EXAMPLE_BIN = os.path.join(ROOT, "tests", "c_abi_example.bin")
+
+
+def build_c_example(verbose: bool = False) -> str:
+    """The plain C consumer of the C ABI used by the tests (gcc, C99, linked against liblbm.so and the
+    HIP runtime; finds liblbm.so next to the package through its run path)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), C_EXAMPLE_SRC, "-L", HERE, "-llbm", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-Wl,-rpath,$ORIGIN/../paper_1912_02018_amd",
+           "-o", C_EXAMPLE_BIN]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return C_EXAMPLE_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_example(verbose=True))
