@@ -236,14 +236,15 @@ def hbm_resident_run(lbm, steps=200):
     from the initial liquid state (no physical warm-up; the same per-step work)."""
     out = _hbm_resident(lbm, PREC["f32"], steps)
     out["f16_store"] = _hbm_resident(lbm, PREC["f16s"], steps)
+    out["rk2"] = _hbm_resident(lbm, PREC["f32"], steps, rk=2)
     return out
 
 
-def _hbm_resident(lbm, prec, steps):
+def _hbm_resident(lbm, prec, steps, rk=4):
     import torch
     from paper_1912_02018_amd.config import cylinder_config
     cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=prec,
-                          warmup=0)
+                          warmup=0, rk_stages=rk)
     if prec >= 2:
         cfg = cfg.replace(rho_ref_shift=lbm.saturation(cfg)["rho_l"])
     sim = lbm.Simulation(cfg)
@@ -255,8 +256,11 @@ def _hbm_resident(lbm, prec, steps):
     mlups = nodes / (ms / steps * 1e-3) / 1e6
     kt = dict(zip(KERNEL_NAMES.values(), timed_region_kernel_ms(sim, 20, ms / steps)[0].values()))
     pname = {v: k for k, v in PREC.items()}[prec]
-    rec = {"workload": f"boiling-cylinder-8192x4096-R256-Re300-rk4-{pname}", "nodes": nodes, "mlups": round(mlups, 1),
-           "ms_per_step": round(ms / steps, 4), "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
+    step_bytes = (18 * STORE_BYTES[prec] + 2 * COMPUTE_BYTES[prec]) * nodes  # populations + T, read and written
+    rec = {"workload": f"boiling-cylinder-8192x4096-R256-Re300-rk{rk}-{pname}", "nodes": nodes, "mlups": round(mlups, 1),
+           "ms_per_step": round(ms / steps, 4),
+           "step_hbm_frac": round(step_bytes / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
            "kernel_hbm_gbs": {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (kt[KERNEL_NAMES[k]] * 1e-3) / 1e9, 1)
                               for k in (0, 1)},
            "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]}}
