@@ -340,12 +340,20 @@ std::vector<unsigned char> cut_link_table(const RunDev &R, int prec)
 // Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD b mod 8), each XCD
 // with its own L2.  Reorder a run's row-major tile list so that XCD j receives a contiguous band of
 // tiles: the halo reads of neighbouring tiles then hit the same L2.
-void xcd_order(std::vector<Tile> &tiles, size_t off, size_t n)
+// XCD-aware order of one run's tiles (row-major on entry): block b runs on XCD b mod 8, so each XCD
+// receives a contiguous band of tiles (their shared halos stay in one L2).  Within a band the tiles
+// for which first(tile) holds are dispatched first: the stream-and-collide tiles next to the cylinder,
+// which take a second memory round trip, then start in the first wave of workgroups instead of
+// finishing last.
+template <typename First>
+void xcd_order(std::vector<Tile> &tiles, size_t off, size_t n, First first)
 {
     const size_t nx = 8;
     if (n < 2 * nx || n % nx != 0) return;
     std::vector<Tile> band(tiles.begin() + off, tiles.begin() + off + n);
     const size_t chunk = n / nx;
+    for (size_t j = 0; j < nx; ++j)
+        std::stable_partition(band.begin() + j * chunk, band.begin() + (j + 1) * chunk, first);
     for (size_t t = 0; t < n; ++t) {
         const size_t j = t / chunk, k = t % chunk;
         tiles[off + k * nx + j] = band[t];
@@ -385,7 +393,15 @@ int build_tiles(lbm_handle *h)
             for (int ty = 0; ty < (R.ny + v.ty - 1) / v.ty; ++ty)
                 for (int tx = 0; tx < (R.nx + v.tx - 1) / v.tx; ++tx) tl[k].push_back(Tile{r, tx, ty, 0});
             cnt.push_back((int)tl[k].size() - off.back());
-            xcd_order(tl[k], off.back(), cnt.back());
+            // stream-and-collide tiles whose region (tile + the 2-node psi halo) meets the cut-link box
+            const int bx0 = R.cyl_x - R.cyl_r - 1, bx1 = R.cyl_x + R.cyl_r + 1;
+            const int by0 = R.cyl_y - R.cyl_r - 1, by1 = R.cyl_y + R.cyl_r + 1;
+            auto near = [&](const Tile &t) {
+                if (k != 0 || R.cyl_r <= 0) return false;
+                const int x0 = t.tx * v.tx - 2, x1 = (t.tx + 1) * v.tx + 1, y0 = t.ty * v.ty - 2, y1 = (t.ty + 1) * v.ty + 1;
+                return x1 >= bx0 && x0 <= bx1 && y1 >= by0 && y0 <= by1;
+            };
+            xcd_order(tl[k], off.back(), cnt.back(), near);
         }
     }
     if ((int)tl[0].size() > h->cap_lbm || (int)tl[1].size() > h->cap_th) return fail(h, LBM_EINVAL, "tile table overflow");
