@@ -126,6 +126,17 @@ int lbm_set_fields(lbm_handle *h, int run, const double *rho, const double *ux, 
  * unspecified), hist [3][ny] (populations 2, 6, 8), T [ny][nx].  Each pointer may be NULL. */
 int lbm_get_state(lbm_handle *h, int run, double *fstar, double *hist, double *T);
 
+/* Checkpoints of the whole handle.  lbm_save copies, byte for byte, every run's current populations
+ * (storage format), outlet history, temperature (compute format, derivatives included in the tangent
+ * precision) and FP64 heat-flux / Nu accumulators, with the step counter and a header, into host_buf
+ * (at least lbm_checkpoint_bytes(h) bytes); it waits for the stream.  lbm_load restores such a
+ * checkpoint into a handle of the same runs (same count, precision and grids; LBM_EINVAL otherwise):
+ * stepping on from it reproduces the uninterrupted run bit for bit, including the time-averaged Nu.
+ * The checkpoint format is that of this library build (not a portable file format). */
+size_t lbm_checkpoint_bytes(const lbm_handle *h);
+int lbm_save(lbm_handle *h, void *host_buf, size_t bytes);
+int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes);
+
 /* Replace the raw state of one run (converted to the storage precision) and set the step
  * counter of the handle to `step`. */
 int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *hist,

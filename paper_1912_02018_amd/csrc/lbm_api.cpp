@@ -921,6 +921,105 @@ int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *his
     return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Checkpoint layout: a header, then per run the current population buffer (storage format), the
+// current outlet history and temperature (compute format) and the FP64 accumulators, byte for byte.
+struct CkptHeader {
+    char magic[8];
+    int32_t n_runs, precision;
+    int64_t step;
+};
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+
+struct CkptPart {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<CkptPart> ckpt_parts(const lbm_handle *h)
+{
+    std::vector<CkptPart> parts;
+    const size_t sb = storage_bytes(h->precision), cb = compute_bytes(h->precision);
+    for (const RunDev &R : h->runs) {
+        const size_t plane = (size_t)R.ny * R.pitch;
+        parts.push_back({R.f[h->pf], 9 * plane * sb});
+        parts.push_back({R.hist[h->ph], 3 * (size_t)R.ny * cb});
+        parts.push_back({R.T[h->pt], plane * cb});
+        parts.push_back({R.acc, sizeof(double) * lbm::kAcc});
+    }
+    return parts;
+}
+
+size_t ckpt_bytes(const lbm_handle *h)
+{
+    size_t b = sizeof(CkptHeader) + sizeof(int32_t) * 2 * (size_t)h->n_runs;
+    for (const CkptPart &p : ckpt_parts(h)) b += p.bytes;
+    return b;
+}
+}  // namespace
+
+extern "C" {
+
+size_t lbm_checkpoint_bytes(const lbm_handle *h) { return h ? ckpt_bytes(h) : 0; }
+
+int lbm_save(lbm_handle *h, void *host_buf, size_t bytes)
+{
+    if (!h) return LBM_EINVAL;
+    if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
+    if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint needs %zu bytes", ckpt_bytes(h));
+    unsigned char *p = (unsigned char *)host_buf;
+    CkptHeader hd;
+    std::memcpy(hd.magic, kCkptMagic, sizeof(hd.magic));
+    hd.n_runs = h->n_runs;
+    hd.precision = h->precision;
+    hd.step = h->step;
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    for (const auto &c : h->cfgs) {
+        const int32_t g[2] = {c.nx, c.ny};
+        std::memcpy(p, g, sizeof(g));
+        p += sizeof(g);
+    }
+    for (const CkptPart &part : ckpt_parts(h)) {
+        HIPCHK(h, hipMemcpyAsync(p, part.dev, part.bytes, hipMemcpyDeviceToHost, h->stream));
+        p += part.bytes;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes)
+{
+    if (!h) return LBM_EINVAL;
+    if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
+    if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint of %zu bytes, this handle's take %zu", bytes, ckpt_bytes(h));
+    const unsigned char *p = (const unsigned char *)host_buf;
+    CkptHeader hd;
+    std::memcpy(&hd, p, sizeof(hd));
+    p += sizeof(hd);
+    if (std::memcmp(hd.magic, kCkptMagic, sizeof(hd.magic)) != 0) return fail(h, LBM_EINVAL, "not a checkpoint");
+    if (hd.n_runs != h->n_runs || hd.precision != h->precision)
+        return fail(h, LBM_EINVAL, "checkpoint of %d runs in precision %d, handle has %d runs in precision %d", hd.n_runs,
+                    hd.precision, h->n_runs, h->precision);
+    for (const auto &c : h->cfgs) {
+        int32_t g[2];
+        std::memcpy(g, p, sizeof(g));
+        p += sizeof(g);
+        if (g[0] != c.nx || g[1] != c.ny) return fail(h, LBM_EINVAL, "checkpoint grid %dx%d differs from %dx%d", g[0], g[1], c.nx, c.ny);
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (const CkptPart &part : ckpt_parts(h)) {
+        HIPCHK(h, hipMemcpyAsync(part.dev, p, part.bytes, hipMemcpyHostToDevice, h->stream));
+        p += part.bytes;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
 int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, double *nu_time_avg)
 {
     int rc = check_run(h, run);

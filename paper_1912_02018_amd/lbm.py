@@ -38,7 +38,7 @@ EXPORTED = [
     "lbm_step_count", "lbm_last_error", "lbm_destroy", "lbm_time_kernel",
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
     "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation", "lbm_profile_steps",
-    "lbm_get_option", "lbm_stream_group_runs",
+    "lbm_get_option", "lbm_stream_group_runs", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
 ]
 OPT_GRAPHS, OPT_STREAM_GROUPS = 0, 1
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
@@ -92,6 +92,10 @@ def load_library():
     L.lbm_autotune.argtypes = [vp, i32, ip]
     L.lbm_set_option.argtypes = [vp, i32, i32]
     L.lbm_get_option.argtypes = [vp, i32]
+    L.lbm_checkpoint_bytes.argtypes = [vp]
+    L.lbm_checkpoint_bytes.restype = C.c_size_t
+    L.lbm_save.argtypes = [vp, vp, C.c_size_t]
+    L.lbm_load.argtypes = [vp, vp, C.c_size_t]
     L.lbm_stream_group_runs.argtypes = [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_profile_steps.argtypes = [vp, i32, dp]
     L.lbm_step_count.argtypes = [vp]
@@ -224,6 +228,18 @@ class Simulation:
 
     def set_graphs(self, enabled: bool):
         self._check(self._L.lbm_set_option(self.h, OPT_GRAPHS, 1 if enabled else 0))
+
+    def save(self) -> bytes:
+        """Checkpoint of every run (raw device state, accumulators and step counter)."""
+        n = self._L.lbm_checkpoint_bytes(self.h)
+        buf = C.create_string_buffer(n)
+        self._check(self._L.lbm_save(self.h, buf, n))
+        return buf.raw
+
+    def load(self, blob: bytes):
+        """Restore a checkpoint written by save() of a handle with the same runs."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(self._L.lbm_load(self.h, buf, len(blob)))
 
     def set_stream_groups(self, groups: int):
         """Step the runs as `groups` contiguous ranges on streams of their own (1: one stream)."""

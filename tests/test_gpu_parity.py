@@ -422,6 +422,41 @@ def test_degenerate_cases(lbm_mod):
     assert np.isfinite(q)
 
 
+@pytest.mark.parametrize("pname", ["f64", "f16", "tangent"])
+def test_checkpoint_resume_bitwise(lbm_mod, pname):
+    """A checkpoint taken mid-run and loaded into another handle (which had stepped elsewhere) resumes
+    the uninterrupted run bit for bit: populations, outlet history, temperature, step counter, the Nu
+    time average and, in the tangent precision, its derivatives; a checkpoint of other runs is refused."""
+    from paper_1912_02018_amd.config import F64_TANGENT, FP16S
+    rl, _ = coex()
+    prec = {"f64": FP64, "f16": FP16S, "tangent": F64_TANGENT}[pname]
+    a_cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=prec, diag_every=3)
+    b_cfg = cylinder_case(nx=80, ny=40, r=5, cx=25, precision=prec, diag_every=4, dTr_wall=0.15)
+    if prec == FP16S:
+        a_cfg, b_cfg = a_cfg.replace(rho_ref_shift=rl), b_cfg.replace(rho_ref_shift=rl)
+    cfgs = [a_cfg, b_cfg] if prec != F64_TANGENT else [a_cfg]
+    ref = lbm_mod.Simulation(cfgs)
+    ref.step(240)
+    first = lbm_mod.Simulation(cfgs)
+    first.step(110)
+    blob = first.save()
+    first.step(9)
+    other = lbm_mod.Simulation(cfgs)
+    other.step(17)
+    other.load(blob)
+    assert other.step_count == 110
+    other.step(130)
+    for r in range(len(cfgs)):
+        assert all(np.array_equal(x, y) for x, y in zip(other.get_state(r)[:3], ref.get_state(r)[:3])), (pname, r)
+        assert other.wall_heat_flux(r) == ref.wall_heat_flux(r), (pname, r)
+    if prec == F64_TANGENT:
+        ga, gb = other.nu_tangent(), ref.nu_tangent()
+        assert all(np.array_equal(np.asarray(x), np.asarray(y)) for x, y in zip(ga, gb))
+    wrong = lbm_mod.Simulation([a_cfg.replace(nx=100)] + cfgs[1:])
+    with pytest.raises(lbm_mod.LBMError):
+        wrong.load(blob)
+
+
 def test_stream_groups_bitwise(lbm_mod):
     """Runs stepped as stream groups (contiguous ranges of runs on streams of their own) end in the
     same states, fields and heat fluxes as the same handle on one stream, through warm-ups that end at
