@@ -7,6 +7,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -63,6 +65,42 @@ struct lbm_handle {
 namespace {
 
 std::string g_create_error;
+
+// Optional roctx ranges around the host entry points (seen by rocprofv3 --marker-trace): the ROCm
+// roctx library is loaded at run time if present; without it the ranges are no-ops.
+struct Roctx {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+    Roctx()
+    {
+        for (const char *name : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"}) {
+            void *lib = dlopen(name, RTLD_NOW | RTLD_LOCAL);
+            if (!lib) continue;
+            push = (int (*)(const char *))dlsym(lib, "roctxRangePushA");
+            pop = (int (*)())dlsym(lib, "roctxRangePop");
+            if (push && pop) return;
+            push = nullptr;
+            pop = nullptr;
+        }
+    }
+};
+
+struct Range {
+    const Roctx &r;
+    explicit Range(const char *name) : r(roctx())
+    {
+        if (r.push) r.push(name);
+    }
+    ~Range()
+    {
+        if (r.pop) r.pop();
+    }
+    static const Roctx &roctx()
+    {
+        static const Roctx instance;
+        return instance;
+    }
+};
 
 int fail(lbm_handle *h, int code, const char *fmt, ...)
 {
@@ -746,6 +784,7 @@ static long long pattern_length(const lbm_handle *h)
 
 int lbm_step(lbm_handle *h, int n_steps)
 {
+    const Range range("lbm_step");
     if (!h) return LBM_EINVAL;
     if (n_steps < 0) return fail(h, LBM_EINVAL, "negative step count");
     bool any_check = false;
@@ -833,6 +872,7 @@ int lbm_step(lbm_handle *h, int n_steps)
 
 int lbm_fields(lbm_handle *h, int run, double *rho, double *ux, double *uy, double *T, uint8_t *mask)
 {
+    const Range range("lbm_fields");
     int rc = check_run(h, run);
     if (rc) return rc;
     const RunDev &R = h->runs[run];
@@ -966,6 +1006,7 @@ size_t lbm_checkpoint_bytes(const lbm_handle *h) { return h ? ckpt_bytes(h) : 0;
 
 int lbm_save(lbm_handle *h, void *host_buf, size_t bytes)
 {
+    const Range range("lbm_save");
     if (!h) return LBM_EINVAL;
     if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
     if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint needs %zu bytes", ckpt_bytes(h));
@@ -992,6 +1033,7 @@ int lbm_save(lbm_handle *h, void *host_buf, size_t bytes)
 
 int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes)
 {
+    const Range range("lbm_load");
     if (!h) return LBM_EINVAL;
     if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
     if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint of %zu bytes, this handle's take %zu", bytes, ckpt_bytes(h));
@@ -1022,6 +1064,7 @@ int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes)
 
 int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, double *nu_time_avg)
 {
+    const Range range("lbm_wall_heat_flux");
     int rc = check_run(h, run);
     if (rc) return rc;
     if ((rc = moments_pass(h, run))) return rc;
@@ -1151,6 +1194,7 @@ extern "C" {
 
 int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms)
 {
+    const Range range("lbm_profile_steps");
     if (!h) return LBM_EINVAL;
     if (!kernel_ms) return fail(h, LBM_EINVAL, "kernel_ms is NULL");
     if (n_steps < 1 || n_steps > LBM_MAX_PROFILE_STEPS)
@@ -1262,6 +1306,7 @@ static int time_pseudo_steps(lbm_handle *h, int n)
 
 int lbm_autotune(lbm_handle *h, int launches, int *best)
 {
+    const Range range("lbm_autotune");
     if (!h) return LBM_EINVAL;
     const std::string key = tune_key(h);
     if (launches < 0) {
