@@ -422,6 +422,36 @@ def test_degenerate_cases(lbm_mod):
     assert np.isfinite(q)
 
 
+def test_unstable_state_is_reported_and_checkpoint_recovers(lbm_mod):
+    """Failure detection, forced from the host (the kernels only compute non-finite values and exit):
+    a NaN density injected at one node makes lbm_step report LBM_EUNSTABLE at its next check;
+    restoring the last checkpoint recovers, and the run then equals the uninterrupted one bit for bit.
+    A wall superheat far beyond the range where the pseudopotential is real (negative radicand at the
+    solid nodes' density and wall temperature, reported as non-finite rather than clamped) fails the same
+    way."""
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP64, check_every=10, diag_every=5)
+    ref = lbm_mod.Simulation(cfg)
+    ref.step(100)
+    sim = lbm_mod.Simulation(cfg)
+    sim.step(50)
+    blob = sim.save()
+    f = sim.fields()
+    rho = f["rho"].copy()
+    rho[20, 40] = np.nan
+    sim.set_fields(rho, f["ux"], f["uy"], f["T"])
+    with pytest.raises(lbm_mod.LBMError) as err:
+        sim.step(20)
+    assert err.value.code == lbm_mod.LBM_EUNSTABLE
+    sim.load(blob)
+    sim.step(50)
+    assert all(np.array_equal(x, y) for x, y in zip(sim.get_state()[:3], ref.get_state()[:3]))
+    assert sim.wall_heat_flux() == ref.wall_heat_flux()
+    hot = lbm_mod.Simulation(cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP64, check_every=1, dTr_wall=1.0))
+    with pytest.raises(lbm_mod.LBMError) as err:
+        hot.step(5)
+    assert err.value.code == lbm_mod.LBM_EUNSTABLE
+
+
 @pytest.mark.parametrize("pname", ["f64", "f16", "tangent"])
 def test_checkpoint_resume_bitwise(lbm_mod, pname):
     """A checkpoint taken mid-run and loaded into another handle (which had stepped elsewhere) resumes
