@@ -237,7 +237,7 @@ template <bool EXT = true> __device__ inline int map_pos(const RunDev &R, int gx
 template <typename C> struct Consts {
     C omega, sigma, gx, gy, rho_gref, rho_w, T_sat, T_w, a, b, Rg, u_in;
     C alpha, inv_cv, kappa, inv_sqrt_Tc, psi_scale, dphi_A, dphi_B;
-    C alpha2w2, alpha2w5, alpha2w8;  // 2 alpha w_k of the diagonal stencil classes
+    C alpha2w1, alpha2w2, alpha2w4, alpha2w5, alpha2w8;  // 2 alpha w_k of the Laplacian's weight classes
     C shiftw[9];
     __device__ explicit Consts(const RunDev &R)
     {
@@ -250,7 +250,8 @@ template <typename C> struct Consts {
         // phi'(T) = dphi_A / sqrt(T) + dphi_B
         dphi_A = seeded<C>(R.dphi_A, R.t_dphi_A);
         dphi_B = seeded<C>(R.dphi_B, R.t_dphi_B);
-        alpha2w2 = (C)(2.0 * W2) * alpha; alpha2w5 = (C)(2.0 * W5) * alpha; alpha2w8 = (C)(2.0 * W8) * alpha;
+        alpha2w1 = (C)(2.0 * W1) * alpha; alpha2w2 = (C)(2.0 * W2) * alpha; alpha2w4 = (C)(2.0 * W4) * alpha;
+        alpha2w5 = (C)(2.0 * W5) * alpha; alpha2w8 = (C)(2.0 * W8) * alpha;
 #pragma unroll
         for (int i = 0; i < 9; ++i) shiftw[i] = (C)(lat_w(i) * R.shift);
     }
@@ -651,12 +652,418 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
 // ------------------------------------------------------------------------------------------
 // The frozen fields rho, u and T^n are loaded with a halo of 2 nodes per stage, so the stages
 // never leave the CU: stage s updates the tile grown by 2 (NS - s) nodes.  Each thread owns a
-// fixed set of positions ("slots") for the whole kernel and keeps their stage-invariant
-// coefficients, T^n and the Runge-Kutta accumulator in registers; only the stage input Y (and
-// rho, u for the invariants) live in LDS.  Slots are numbered ring by ring outwards from the
-// tile, so the positions of a later, smaller stage are a prefix of the numbering and whole
-// wavefronts drop out as the stages shrink.
+// fixed set of slots for the whole kernel, a slot being two vertically adjacent positions, and
+// keeps their stage-invariant coefficients in registers (T^n and the Runge-Kutta accumulator too,
+// unless the thread has many slots); LDS holds the stage inputs and rho, u for the invariants.
+// A slot reads the 6 x 5 window of its two positions once and forms the row sums and differences
+// that both positions' stencils are built from.  Slots are numbered ring by ring outwards from the tile (the halo of a
+// stage is 2 nodes, so every ring is made of whole pairs), so the slots of a later, smaller stage
+// are a prefix of the numbering and whole wavefronts drop out as the stages shrink.
 template <int TX, int TY, int NS> struct ThGeom {
+    static_assert(TY % 2 == 0, "slots pair the rows of the tile");
+    static constexpr int H = 2 * NS;
+    // region of RX x RH positions stored with an odd row stride RW (the ring slots of a wavefront
+    // are short row pieces a stride apart, which an even stride would put on few LDS banks)
+    static constexpr int RX = TX + 2 * H, RW = RX + 1, RH = TY + 2 * H, RN = RW * RH, TN = TX * TY;
+    // slots updated by stage s
+    static constexpr int count(int s) { return (TX + 4 * (NS - s)) * (TY + 4 * (NS - s)) / 2; }
+    static constexpr int NSLOT = count(1), TSLOT = TN / 2;
+};
+
+template <int TX, int TY, int NS> struct SlotTable {
+    unsigned short pos[ThGeom<TX, TY, NS>::NSLOT];  // LDS position of the slot's upper node
+};
+
+template <int TX, int TY, int NS> constexpr SlotTable<TX, TY, NS> make_slots()
+{
+    using G = ThGeom<TX, TY, NS>;
+    SlotTable<TX, TY, NS> t{};
+    int r = 0;
+    for (int yp = 0; yp < TY / 2; ++yp)
+        for (int x = 0; x < TX; ++x) t.pos[r++] = (unsigned short)((G::H + 2 * yp) * G::RW + G::H + x);
+    // ring k: the tile grown by 2k nodes minus the tile grown by 2(k - 1); its top and bottom
+    // bands are one row of pairs each, its sides columns of pairs
+    for (int k = 1; k < NS; ++k) {
+        const int o = G::H - 2 * k, A = TX + 4 * (k - 1), B = TY + 4 * (k - 1);
+        for (int xx = 0; xx < A + 4; ++xx) t.pos[r++] = (unsigned short)(o * G::RW + o + xx);
+        for (int xx = 0; xx < A + 4; ++xx) t.pos[r++] = (unsigned short)((o + B + 2) * G::RW + o + xx);
+        for (int yp = 0; yp < B / 2; ++yp)
+            for (int q = 0; q < 4; ++q) t.pos[r++] = (unsigned short)((o + 2 + 2 * yp) * G::RW + o + (q < 2 ? q : A + q));
+    }
+    return t;
+}
+
+template <int TX, int TY, int NS> __constant__ const SlotTable<TX, TY, NS> kSlots = make_slots<TX, TY, NS>();
+
+// Sums and differences of opposite neighbours along one row of a 5-wide window (r: its column -2):
+// h0 = a(0), s1 = a(1) + a(-1), s2 = a(2) + a(-2), d1 = a(1) - a(-1), d2 = a(2) - a(-2)
+template <typename C> struct RowQ {
+    C h0, s1, s2, d1, d2;
+};
+template <typename C> __device__ inline RowQ<C> row_q(const C *r)
+{
+    return RowQ<C>{r[2], r[3] + r[1], r[4] + r[0], r[3] - r[1], r[4] - r[0]};
+}
+
+// x and y components of sum_k w_k a(x + e_k) e_k at the node of row q[2] (q: rows -2 .. 2), the
+// opposite-neighbour pairs of each weight class grouped by rows
+template <typename C> __device__ inline C grad_x(const RowQ<C> *q)
+{
+    return (C)W1 * q[2].d1 + (C)(2 * W4) * q[2].d2 + (C)W2 * (q[3].d1 + q[1].d1) + (C)(2 * W5) * (q[3].d2 + q[1].d2) +
+           (C)W5 * (q[4].d1 + q[0].d1) + (C)(2 * W8) * (q[4].d2 + q[0].d2);
+}
+template <typename C> __device__ inline C grad_y(const RowQ<C> *q)
+{
+    return (C)W1 * (q[3].h0 - q[1].h0) + (C)(2 * W4) * (q[4].h0 - q[0].h0) + (C)W2 * (q[3].s1 - q[1].s1) +
+           (C)W5 * (q[3].s2 - q[1].s2) + (C)(2 * W5) * (q[4].s1 - q[0].s1) + (C)(2 * W8) * (q[4].s2 - q[0].s2);
+}
+
+template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
+    using G = ThGeom<TX, TY, NS>;
+    static constexpr int H = G::H, RW = G::RW, RN = G::RN, NSLOT = G::NSLOT;
+    static constexpr int ITER = (NSLOT + NT - 1) / NT;
+
+    // Once the stage invariants are formed, rho holds every other stage input (and, with RK_IN_LDS,
+    // ux the slots' T^n and uy their Runge-Kutta accumulators, by position)
+    struct Smem {
+        C Y[RN], rho[RN], ux[RN], uy[RN];
+    };
+    // coefficients of L(Y) at the two nodes of a slot ([n]: upper / lower; 8 registers per node):
+    // u/12, v/12 and |u| c_d, |v| c_d of the upwind convection, the density-gradient coefficients
+    // gx, gy, the centre coefficient c0 (the Laplacian's and the convection's centre weights and the
+    // linear part c1 of the source) and c2 of sqrt(Y)
+    struct Coef {
+        C u12[2], v12[2], au[2], av[2], gx[2], gy[2], c0[2], c2[2];
+        C al[PH ? 2 : 1];  // alpha at the node (phase-dependent properties)
+    };
+    // When a thread's last slot lies outside every stage after the first (the outer ring of a tile
+    // with few threads), that slot forms its stage-1 k together with its invariants and keeps only
+    // that, not its coefficients
+    static constexpr bool LAST_S1 = ITER > 1 && G::count(2) <= NT * (ITER - 1);
+    static constexpr int NCOEF = LAST_S1 ? ITER - 1 : ITER;
+    // With many slots per thread, T^n and the accumulators of the slots' nodes live in LDS (in ux and
+    // uy, free once the invariants are formed) rather than in registers; the arithmetic is the same
+    static constexpr bool RK_IN_LDS = ITER >= 3;
+    static constexpr int NRK = RK_IN_LDS ? 1 : ITER;
+    // per-slot state, in registers
+    struct Slots {
+        // LDS position of the upper node (low 16 bits) and the one the operator is evaluated at
+        // for it (high 16 bits; both nodes held: no evaluation)
+        unsigned pos[ITER];
+        __device__ int own(int j) const { return (int)(pos[j] & 0xffffu); }
+        __device__ int ev(int j) const { return (int)(pos[j] >> 16); }
+        __device__ bool evaluated(int j) const { return ((hold >> (2 * j)) & 3u) != 3u; }
+        unsigned hold;   // bit 2 j + n: node n of slot j keeps its value (solid, inlet or wall ghost)
+        Coef cf[NCOEF];
+        C k1[2];         // LAST_S1: stage-1 k of the last slot
+        C T0[NRK][2], acc[NRK][2];  // (!RK_IN_LDS)
+    };
+
+    // right-hand side L(Y) of eq. energy at both nodes of a slot with coefficients f, evaluated at
+    // LDS positions c and c + RW of the stage input Y
+    __device__ static void rhs(const C *Y, const Consts<C> &K, const Coef &f, int c, bool phase, C k[2])
+    {
+        // the 6 x 5 window read as positive offsets from its lowest corner
+        const C *b = Y + opaque_index(c - 2 * RW - 2);
+        RowQ<C> q[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) q[r] = row_q(b + r * RW);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const RowQ<C> *w = q + n;  // rows -2 .. 2 of node n
+            const C y0 = w[2].h0;
+            // sums and differences of the column's opposite neighbours
+            const C S1 = w[3].h0 + w[1].h0, S2 = w[4].h0 + w[0].h0;
+            const C D1 = w[3].h0 - w[1].h0, D2 = w[4].h0 - w[0].h0;
+            // Laplacian without its centre term: 2 alpha sum_k w_k Y(x + e_k), by weight class
+            const C l1 = w[2].s1 + S1, l4 = w[2].s2 + S2, l2 = w[3].s1 + w[1].s1;
+            const C l5 = (w[3].s2 + w[1].s2) + (w[4].s1 + w[0].s1), l8 = w[4].s2 + w[0].s2;
+            // (a run without phase-dependent properties takes the same arithmetic in either launch,
+            // so batching it with runs that have them does not change its result)
+            C lap;
+            if (PH && phase)
+                lap = f.al[PH ? n : 0] * ((C)(2 * W1) * l1 + (C)(2 * W4) * l4 + (C)(2 * W2) * l2 +
+                                             (C)(2 * W5) * l5 + (C)(2 * W8) * l8);
+            else
+                lap = K.alpha2w1 * l1 + K.alpha2w4 * l4 + K.alpha2w2 * l2 + K.alpha2w5 * l5 + K.alpha2w8 * l8;
+            // third-order upwind-biased convection without its centre term
+            const C conv = f.u12[n] * ((C)8 * w[2].d1 - w[2].d2) + f.au[n] * (w[2].s2 - (C)4 * w[2].s1) +
+                           f.v12[n] * ((C)8 * D1 - D2) + f.av[n] * (S2 - (C)4 * S1);
+            // centre: Laplacian, convection and the linear part of the pressure-work source
+            // T (c1 + c2 phi'(T)), phi'(T) = A / sqrt(T) + B
+            k[n] = (lap - conv) + f.gx[n] * grad_x(w) + f.gy[n] * grad_y(w) + f.c0[n] * y0 +
+                   f.c2[n] * Ar<C>::sqrt_(y0);
+        }
+    }
+
+    // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input.
+    // The stage inputs alternate between two LDS arrays (Y and, once the stage invariants are
+    // formed, the density's), so a slot writes its next input as soon as its k is known: one barrier
+    // per stage.  Stage 1 also copies the held positions into the second array.
+    template <int s>
+    __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S, bool phase)
+    {
+        constexpr int CNT = G::count(s);
+        const C *Yin = (s & 1) ? sm.Y : sm.rho;
+        C *Yout = (s & 1) ? sm.rho : sm.Y;
+#pragma unroll
+        for (int j = 0; j < ITER; ++j) {
+            const int r = threadIdx.x + NT * j;
+            if (r >= CNT) continue;
+            C kv[2] = {(C)0, (C)0};
+            if (LAST_S1 && s == 1 && j == ITER - 1) { kv[0] = S.k1[0]; kv[1] = S.k1[1]; }
+            else if (S.evaluated(j)) rhs(Yin, K, S.cf[j < NCOEF ? j : 0], S.ev(j), phase, kv);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const int o = S.own(j) + n * RW;
+                if ((S.hold >> (2 * j + n)) & 1u) {
+                    if constexpr (s == 1) Yout[o] = Yin[o];
+                    continue;
+                }
+                const C k = kv[n];
+                const int jr = RK_IN_LDS ? 0 : j;
+                C t0, a;
+                if constexpr (s == 1) {
+                    t0 = Yin[o];
+                    if constexpr (RK_IN_LDS) sm.ux[o] = t0;
+                    else S.T0[jr][n] = t0;
+                } else {
+                    t0 = RK_IN_LDS ? sm.ux[o] : S.T0[jr][n];
+                    a = RK_IN_LDS ? sm.uy[o] : S.acc[jr][n];
+                }
+                if constexpr (NS == 4) {
+                    if constexpr (s == 1) { a = k; Yout[o] = t0 + (C)0.5 * k; }
+                    else if constexpr (s == 2) { a += (C)2 * k; Yout[o] = t0 + (C)0.5 * k; }
+                    else if constexpr (s == 3) { a += (C)2 * k; Yout[o] = t0 + k; }
+                    else { a = t0 + (a + k) * (C)(1.0 / 6.0); }
+                } else {
+                    if constexpr (s == 1) { a = k; Yout[o] = t0 + k; }
+                    else { a = t0 + (C)0.5 * (a + k); }
+                }
+                if constexpr (RK_IN_LDS) sm.uy[o] = a;
+                else S.acc[jr][n] = a;
+            }
+        }
+        if constexpr (s < NS) __syncthreads();  // the next stage input is complete
+    }
+};
+
+// OCC > 0: ask the compiler for at least OCC waves per SIMD (a register budget)
+template <typename C, int TX, int TY, int NS, int NT, bool PH, int OCC = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void k_thermal(
+    const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt, long long step)
+{
+    static_assert(!is_dual<C>, "the tangent precision takes k_thermal_tan");
+    using Th = Thermal<C, TX, TY, NS, NT, PH>;
+    using G = typename Th::G;
+    constexpr int H = G::H, RX = G::RX, RW = G::RW, RH = G::RH, TN = G::TN, NSLOT = G::NSLOT, TSLOT = G::TSLOT;
+    constexpr int ITER = Th::ITER;
+    __shared__ typename Th::Smem sm;
+
+    const Tile t = tiles[blockIdx.x];
+    const RunDev &R = runs[t.run];
+    const int x0 = t.tx * TX, y0 = t.ty * TY;
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    if (step < R.warmup || R.rk == 0) {
+        // this run does not advance its temperature in this step: carry T over
+        const gp<const C> Tin = gin<C>(R.T[pt]);
+        const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
+        for (int q = threadIdx.x; q < TN; q += NT) {
+            const int gx = x0 + q % TX, gy = y0 + q / TX;
+            if (gx < nx && gy < ny) Tout[(size_t)gy * P + gx] = Tin[(size_t)gy * P + gx];
+        }
+        return;
+    }
+    const Consts<C> K(R);
+
+    // LDS positions of this thread's slots, fetched from the constant table first so that their
+    // latency overlaps the field loads
+    int spos[ITER];
+#pragma unroll
+    for (int j = 0; j < ITER; ++j) {
+        const int r = threadIdx.x + NT * j;
+        spos[j] = r < NSLOT ? (int)kSlots<TX, TY, NS>.pos[r] : 0;
+    }
+
+    // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
+    {
+        // every position of the thread: all loads are issued before the first LDS write (one memory
+        // round trip); ghost positions map to valid nodes, so every load is in bounds, and the
+        // ghost values replace the loaded ones afterwards
+        constexpr int IL = (RX * RH + NT - 1) / NT;
+        C lr[IL], lu[IL], lv[IL], lt[IL];
+        unsigned inlet = 0, wall = 0;
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
+            const int lx = n % RX, ly = n / RX;
+            int rx, ry;
+            const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+            const unsigned idx = (unsigned)(ry * P + rx);
+            if (kind == INLET_GHOST) inlet |= 1u << i;
+            if (PH && kind == WALL_GHOST) wall |= 1u << i;
+            lr[i] = ld_at<C>(R.rho, idx);
+            lu[i] = ld_at<C>(R.ux, idx);
+            lv[i] = ld_at<C>(R.uy, idx);
+            lt[i] = ld_at<C>(R.T[pt], idx);
+        }
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            // (a thread past the region rewrites the last position with the value loaded for it,
+            // so that no load is sunk behind a branch)
+            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
+            const int p = (n / RX) * RW + n % RX;
+            const bool w = (wall >> i) & 1u;
+            sm.rho[p] = w ? K.rho_w : lr[i];
+            sm.ux[p] = w ? (C)0 : lu[i];
+            sm.uy[p] = w ? (C)0 : lv[i];
+            sm.Y[p] = ((inlet >> i) & 1u) ? K.T_sat : (w ? K.T_w : lt[i]);
+        }
+    }
+    __syncthreads();
+
+    // slots and their stage-invariant coefficients:
+    //   gx, gy = alpha grad(rho)/rho;  source(T) = c1 T + c2 sqrt(T) with
+    //   D = div(u)/(rho cv), c1 = -D R rho/(1 - b rho) + B D a rho^2/(1 + 2 b rho - b^2 rho^2),
+    //   c2 = A D a rho^2/(1 + 2 b rho - b^2 rho^2), phi'(T) = A/sqrt(T) + B
+    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
+    const int out_c = (nx - 1) - (x0 - H);  // LDS column of the last domain column
+    const bool phase = PH && R.phase_props;
+    typename Th::Slots S;
+    S.hold = 0;
+    S.k1[0] = S.k1[1] = 0;
+    // (a stage-1-only last slot first, while no other slot's coefficients occupy registers)
+#pragma unroll
+    for (int jj = 0; jj < ITER; ++jj) {
+        const int j = Th::LAST_S1 ? (jj == 0 ? ITER - 1 : jj - 1) : jj;
+        S.pos[j] = 0;
+        const bool last_s1 = Th::LAST_S1 && j == ITER - 1;
+        typename Th::Coef tmp;
+        typename Th::Coef &f = last_s1 ? tmp : S.cf[j < Th::NCOEF ? j : 0];
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            f.gx[n] = f.gy[n] = f.c0[n] = f.c2[n] = 0;
+            f.u12[n] = f.v12[n] = f.au[n] = f.av[n] = 0;
+            f.al[PH ? n : 0] = 0;
+        }
+        const int r = threadIdx.x + NT * j;
+        if (r >= NSLOT) continue;
+        const int p = spos[j];
+        const int lx = p % RW, ly = p / RW;
+        int rx, ry;
+        const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        S.pos[j] = (unsigned)p;
+        // the kind of a position depends on its column only, so both nodes of a slot share it
+        if (kind == INLET_GHOST || kind == WALL_GHOST) {
+            S.hold |= 3u << (2 * j);
+            continue;
+        }
+        const int ry1 = ry + 1 == ny ? 0 : ry + 1;
+        const unsigned hj = (solid_at(R, rx, ry) ? 1u : 0u) | (solid_at(R, rx, ry1) ? 2u : 0u);
+        S.hold |= hj << (2 * j);
+        if (hj == 3u) continue;
+        // an outlet ghost evaluates the operator at the last column of its row
+        const int c = kind == OUTLET_GHOST ? ly * RW + out_c : p;
+        S.pos[j] |= (unsigned)c << 16;
+        const int corner = opaque_index(c - 2 * RW - 2);
+        // one field at a time (its 6 x 5 window, then the stencils it feeds), which bounds the
+        // registers the windows hold beside the slots' coefficients
+        C rho[2], gxr[2], gyr[2], u[2], v[2], div[2];
+        {
+            RowQ<C> q[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.rho + corner + k * RW);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                rho[n] = q[n + 2].h0;
+                gxr[n] = grad_x(q + n);
+                gyr[n] = grad_y(q + n);
+            }
+        }
+        {
+            RowQ<C> q[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.ux + corner + k * RW);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                u[n] = q[n + 2].h0;
+                div[n] = grad_x(q + n);
+            }
+        }
+        {
+            RowQ<C> q[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.uy + corner + k * RW);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                v[n] = q[n + 2].h0;
+                div[n] = div[n] + grad_y(q + n);
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            if ((hj >> n) & 1u) continue;  // a solid node: its coefficients stay zero
+            const C ir = Ar<C>::rcp(rho[n]);
+            // (1/(rho cv)) div(lambda grad T) with lambda = rho cv alpha(rho):
+            //   alpha (lap T + grad rho . grad T / rho) + alpha'(rho) grad rho . grad T
+            C dal;
+            const C al = alpha_at<PH>(R, K, rho[n], dal);
+            const C gcoef = al * ir + dal;
+            const C gx = gcoef * gxr[n];
+            const C gy = gcoef * gyr[n];
+            const C D = div[n] * ir * K.inv_cv;
+            const C d1 = (C)1 - K.b * rho[n];
+            const C d2 = (C)1 + (C)2 * K.b * rho[n] - K.b * K.b * rho[n] * rho[n];
+            const C A2 = D * K.a * rho[n] * rho[n] * Ar<C>::rcp(d2);
+            const C c1 = -D * rho[n] * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
+            f.c2[n] = K.dphi_A * A2;
+            // third-order upwind-biased convection per axis:
+            //   u (8 d1 - d2) / 12 + |u| c_d (S2 - 4 S1 + 6 Y)   (d, S: differences / sums of the pair)
+            const C au = absval(u[n]) * cd, av = absval(v[n]) * cd;
+            f.gx[n] = gx;
+            f.gy[n] = gy;
+            if constexpr (PH) f.al[n] = al;
+            f.u12[n] = u[n] * (C)(1.0 / 12.0);
+            f.v12[n] = v[n] * (C)(1.0 / 12.0);
+            f.au[n] = au;
+            f.av[n] = av;
+            f.c0[n] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
+        }
+        // (T^n, the stage-1 input, is not written before the barrier that follows)
+        if (last_s1) {
+            Th::rhs(sm.Y, K, tmp, c, phase, S.k1);
+        }
+    }
+
+    __syncthreads();  // the density array is read by every slot's invariants before stage 1 reuses it
+    Th::template stage<1>(sm, K, S, phase);
+    Th::template stage<2>(sm, K, S, phase);
+    if constexpr (NS == 4) {
+        Th::template stage<3>(sm, K, S, phase);
+        Th::template stage<4>(sm, K, S, phase);
+    }
+
+    // the tile's slots come first
+#pragma unroll
+    for (int j = 0; j < ITER; ++j) {
+        const int r = threadIdx.x + NT * j;
+        if (NT * j >= TSLOT || r >= TSLOT) continue;
+        const int gx = x0 + r % TX, gy = y0 + 2 * (r / TX);
+        if (gx >= nx) continue;
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+            if (gy + n < ny)
+                *at<C>(R.T[pt ^ 1], (unsigned)((gy + n) * P + gx)) =
+                    ((S.hold >> (2 * j + n)) & 1u) ? K.T_w
+                                                   : (Th::RK_IN_LDS ? sm.uy[S.own(j) + n * RW] : S.acc[Th::RK_IN_LDS ? 0 : j][n]);
+    }
+}
+
+// k_thermal_tan: the same temperature step in the tangent precision, one position per slot (the
+// 40-byte values of a slot pair's windows would not fit the registers); slots, stages and the
+// stencils' grouping by weight class as in k_thermal, with the opposite-neighbour differences of a
+// single 5 x 5 window
+template <int TX, int TY, int NS> struct ThGeom1 {
     static constexpr int H = 2 * NS;
     // region of RX x RH positions stored with an odd row stride RW (the ring slots of a wavefront
     // are short row pieces a stride apart, which an even stride would put on few LDS banks)
@@ -665,14 +1072,14 @@ template <int TX, int TY, int NS> struct ThGeom {
     static constexpr int NSLOT = count(1);
 };
 
-template <int TX, int TY, int NS> struct SlotTable {
-    unsigned short pos[ThGeom<TX, TY, NS>::NSLOT];
+template <int TX, int TY, int NS> struct SlotTable1 {
+    unsigned short pos[ThGeom1<TX, TY, NS>::NSLOT];
 };
 
-template <int TX, int TY, int NS> constexpr SlotTable<TX, TY, NS> make_slots()
+template <int TX, int TY, int NS> constexpr SlotTable1<TX, TY, NS> make_slots1()
 {
-    using G = ThGeom<TX, TY, NS>;
-    SlotTable<TX, TY, NS> t{};
+    using G = ThGeom1<TX, TY, NS>;
+    SlotTable1<TX, TY, NS> t{};
     int r = 0;
     for (int y = 0; y < TY; ++y)
         for (int x = 0; x < TX; ++x) t.pos[r++] = (unsigned short)((G::H + y) * G::RW + G::H + x);
@@ -689,10 +1096,10 @@ template <int TX, int TY, int NS> constexpr SlotTable<TX, TY, NS> make_slots()
     return t;
 }
 
-template <int TX, int TY, int NS> __constant__ const SlotTable<TX, TY, NS> kSlots = make_slots<TX, TY, NS>();
+template <int TX, int TY, int NS> __constant__ const SlotTable1<TX, TY, NS> kSlots1 = make_slots1<TX, TY, NS>();
 
-template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
-    using G = ThGeom<TX, TY, NS>;
+template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal1 {
+    using G = ThGeom1<TX, TY, NS>;
     static constexpr int H = G::H, RW = G::RW, RN = G::RN, TN = G::TN, NSLOT = G::NSLOT;
     static constexpr int ITER = (NSLOT + NT - 1) / NT;
 
@@ -795,10 +1202,10 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
 };
 
 template <typename C, int TX, int TY, int NS, int NT, bool PH>
-__global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt,
+__global__ __launch_bounds__(NT) void k_thermal_tan(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt,
                                                 long long step)
 {
-    using Th = Thermal<C, TX, TY, NS, NT, PH>;
+    using Th = Thermal1<C, TX, TY, NS, NT, PH>;
     constexpr int H = Th::H, RX = Th::G::RX, RW = Th::RW, RH = Th::G::RH, TN = Th::TN, NSLOT = Th::NSLOT;
     constexpr int ITER = Th::ITER;
     __shared__ typename Th::Smem sm;
@@ -825,12 +1232,12 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
 #pragma unroll
     for (int j = 0; j < ITER; ++j) {
         const int r = threadIdx.x + NT * j;
-        spos[j] = r < NSLOT ? (int)kSlots<TX, TY, NS>.pos[r] : 0;
+        spos[j] = r < NSLOT ? (int)kSlots1<TX, TY, NS>.pos[r] : 0;
     }
 
     // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
-    if constexpr (is_dual<C>) {
-        // (40-byte values: one position at a time keeps the registers of the tangent kernel low)
+    {
+        // (40-byte values: one position at a time keeps the registers low)
         for (int n = threadIdx.x; n < RX * RH; n += NT) {
             const int lx = n % RX, ly = n / RX, p = ly * RW + lx;
             int rx, ry;
@@ -840,39 +1247,6 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
             sm.ux[p] = ld_at<C>(R.ux, idx);
             sm.uy[p] = ld_at<C>(R.uy, idx);
             sm.Y[p] = kind == INLET_GHOST ? K.T_sat : ld_at<C>(R.T[pt], idx);
-        }
-    } else {
-        // every position of the thread: all loads are issued before the first LDS write (one memory
-        // round trip); ghost positions map to valid nodes, so every load is in bounds, and the
-        // ghost values replace the loaded ones afterwards
-        constexpr int IL = (RX * RH + NT - 1) / NT;
-        C lr[IL], lu[IL], lv[IL], lt[IL];
-        unsigned inlet = 0, wall = 0;
-#pragma unroll
-        for (int i = 0; i < IL; ++i) {
-            const int n = min(threadIdx.x + NT * i, RX * RH - 1);
-            const int lx = n % RX, ly = n / RX;
-            int rx, ry;
-            const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
-            const unsigned idx = (unsigned)(ry * P + rx);
-            if (kind == INLET_GHOST) inlet |= 1u << i;
-            if (PH && kind == WALL_GHOST) wall |= 1u << i;
-            lr[i] = ld_at<C>(R.rho, idx);
-            lu[i] = ld_at<C>(R.ux, idx);
-            lv[i] = ld_at<C>(R.uy, idx);
-            lt[i] = ld_at<C>(R.T[pt], idx);
-        }
-#pragma unroll
-        for (int i = 0; i < IL; ++i) {
-            // (a thread past the region rewrites the last position with the value loaded for it,
-            // so that no load is sunk behind a branch)
-            const int n = min(threadIdx.x + NT * i, RX * RH - 1);
-            const int p = (n / RX) * RW + n % RX;
-            const bool w = (wall >> i) & 1u;
-            sm.rho[p] = w ? K.rho_w : lr[i];
-            sm.ux[p] = w ? (C)0 : lu[i];
-            sm.uy[p] = w ? (C)0 : lv[i];
-            sm.Y[p] = ((inlet >> i) & 1u) ? K.T_sat : (w ? K.T_w : lt[i]);
         }
     }
     __syncthreads();
@@ -953,6 +1327,7 @@ __global__ __launch_bounds__(NT) void k_thermal(const RunDev *__restrict__ runs,
         *at<C>(R.T[pt ^ 1], (unsigned)(gy * P + gx)) = S.ev[j] < 0 ? K.T_w : S.acc[j];
     }
 }
+
 
 // ------------------------------------------------------------------------------------------
 // Diagnostics: FP64 mass and wall heat flux, fixed reduction order
@@ -1088,7 +1463,9 @@ static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 51
                                  {32, 8, 256, 6},  {64, 8, 512, 6},  {64, 8, 512, 7}};
 static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
-static const Variant kTh32[] = {{64, 32, 512}, {32, 32, 512}, {64, 32, 1024}, {32, 32, 256}};
+// (64 x 32 with 512 threads: also with a register budget of 4 waves per SIMD, which gives it a
+// second workgroup per CU)
+static const Variant kTh32[] = {{64, 32, 512, 0}, {32, 32, 512, 0}, {64, 32, 1024, 0}, {32, 32, 256, 0}, {64, 32, 512, 4}};
 static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
 // tangent precision (40-byte values): one small tile each (the RK4 temperature tile with its
 // 8-node halo stays within the 160 KB of LDS)
@@ -1099,7 +1476,7 @@ int variant_count(int precision, int kernel)
 {
     if (precision == 4) return 1;
     if (kernel == 0) return precision == 0 ? 2 : 7;
-    return precision == 0 ? 2 : 4;
+    return precision == 0 ? 2 : 5;
 }
 
 Variant variant_shape(int precision, int kernel, int v)
@@ -1180,23 +1557,29 @@ hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, cons
     }
 }
 
-template <typename C, int TX, int TY, int NT>
+template <typename C, int TX, int TY, int NT, int OCC = 0>
 static hipError_t th_go(int rk, bool phase, const RunDev *runs, const Tile *tiles, int n, int pt, long long step,
                         hipStream_t st, const Timing *tm)
 {
     if constexpr (!is_dual<C>) {
         if (phase) {
-            if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, true>, n, NT, st, tm, runs, tiles, pt, step);
-            else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, true>, n, NT, st, tm, runs, tiles, pt, step);
+            if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, true, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+            else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, true, OCC>, n, NT, st, tm, runs, tiles, pt, step);
             else return hipErrorInvalidValue;
             return hipGetLastError();
         }
     } else {
         if (phase) return hipErrorInvalidValue;
     }
-    if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
-    else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
-    else return hipErrorInvalidValue;
+    if constexpr (is_dual<C>) {
+        if (rk == 4) dispatch(k_thermal_tan<C, TX, TY, 4, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
+        else if (rk == 2) dispatch(k_thermal_tan<C, TX, TY, 2, NT, false>, n, NT, st, tm, runs, tiles, pt, step);
+        else return hipErrorInvalidValue;
+    } else {
+        if (rk == 4) dispatch(k_thermal<C, TX, TY, 4, NT, false, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else if (rk == 2) dispatch(k_thermal<C, TX, TY, 2, NT, false, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1220,6 +1603,7 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
     case 1: return th_go<float, 32, 32, 512>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 4: return th_go<float, 64, 32, 512, 4>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     default: return hipErrorInvalidValue;
     }
 }
