@@ -116,6 +116,35 @@ def test_ragged_tiles_rk2_kawamura_kuwahara_fp64(lbm_mod):
     compare(sim, ref, "cylinder 100x50 R6 RK2 KK 300 steps", u_ref=cfg.u_in)
 
 
+@pytest.mark.parametrize("rk", [4, 2])
+def test_odd_row_count_every_thermal_variant_fp64(lbm_mod, rk):
+    """The temperature kernel updates positions in vertically adjacent pairs: with an odd number of
+    rows the last pair of a tile column reaches one row past the domain (a periodic copy, computed and
+    not stored).  Every temperature-kernel variant against the oracle, on a channel and on a tiny
+    periodic box whose halo spans several periods."""
+    cfg = cylinder_case(nx=90, ny=45, r=6, cx=28, rk=rk)
+    ref = oracle.Sim(cfg)
+    ref.step(150)
+    rl, rv = coex()
+    tiny = LBMConfig(nx=6, ny=5, bc_x=BC_PERIODIC, rk_stages=rk, nu=0.1, alpha_T=0.05, rho_l=rl, rho_v=rv,
+                     precision=FP64)
+    fields = inputs.random_fields(6, 5, rl, 1e-3, 1e-3, seed=21)
+    T = np.full((5, 6), 0.86 * COEX_TC()) * (1 + inputs.uniform_noise(22, (5, 6), 1e-3))
+    tiny_ref = oracle.Sim(tiny)
+    tiny_ref.set_fields(*fields, T)
+    tiny_ref.step(100)
+    for vt in range(len(lbm_mod.Simulation(cfg).variants(1))):
+        sim = lbm_mod.Simulation(cfg)
+        sim.set_variant(1, vt)
+        sim.step(150)
+        compare(sim, ref, f"channel 90x45 RK{rk} thermal variant {vt}", u_ref=cfg.u_in)
+        t = lbm_mod.Simulation(tiny)
+        t.set_variant(1, vt)
+        t.set_fields(*fields, T)
+        t.step(100)
+        compare(t, tiny_ref, f"periodic 6x5 RK{rk} thermal variant {vt}")
+
+
 def test_periodic_array_with_gravity_fp64(lbm_mod):
     rl, rv = coex()
     cfg = LBMConfig(nx=72, ny=40, bc_x=BC_PERIODIC, cyl_x=36, cyl_y=20, cyl_r=7, rk_stages=4,
