@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the kernel arguments arrive preloaded in scalar registers: one dependent memory round trip
+    # fewer before a workgroup's first loads (its tile entry, then its run's parameters)
+    "-mllvm", "-amdgpu-kernarg-preload-count=8",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
