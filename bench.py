@@ -234,13 +234,38 @@ def hbm_resident_run(lbm, steps=200):
     """The Re 300 channel scaled by 8 (8192x4096, cylinder R 256 at x 2048): a state of ~3 GB that
     no cache holds, with FP32 populations and with FP16 storage (shift w_i rho_l).  Coupled steps
     from the initial liquid state (no physical warm-up; the same per-step work)."""
-    out = _hbm_resident(lbm, PREC["f32"], steps)
-    out["f16_store"] = _hbm_resident(lbm, PREC["f16s"], steps)
-    out["rk2"] = _hbm_resident(lbm, PREC["f32"], steps, rk=2)
+    import torch
+    copy_gbs = copy_bandwidth(torch)
+    out = _hbm_resident(lbm, PREC["f32"], steps, copy_gbs=copy_gbs)
+    out["f16_store"] = _hbm_resident(lbm, PREC["f16s"], steps, copy_gbs=copy_gbs)
+    out["rk2"] = _hbm_resident(lbm, PREC["f32"], steps, rk=2, copy_gbs=copy_gbs)
+    out["copy_gbs"] = round(copy_gbs, 1)
     return out
 
 
-def _hbm_resident(lbm, prec, steps, rk=4):
+def copy_bandwidth(torch, mib=1024, reps=20):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy of `mib` MiB (torch's
+    copy kernel), bytes read + written per second over `reps` back-to-back copies."""
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def _hbm_resident(lbm, prec, steps, rk=4, copy_gbs=None):
     import torch
     from paper_1912_02018_amd.config import cylinder_config
     cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=prec,
@@ -260,6 +285,7 @@ def _hbm_resident(lbm, prec, steps, rk=4):
     rec = {"workload": f"boiling-cylinder-8192x4096-R256-Re300-rk{rk}-{pname}", "nodes": nodes, "mlups": round(mlups, 1),
            "ms_per_step": round(ms / steps, 4),
            "step_hbm_frac": round(step_bytes / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "step_copy_frac": round(step_bytes / (ms / steps * 1e-3) / 1e9 / copy_gbs, 4) if copy_gbs else None,
            "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
            "kernel_hbm_gbs": {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (kt[KERNEL_NAMES[k]] * 1e-3) / 1e9, 1)
                               for k in (0, 1)},
