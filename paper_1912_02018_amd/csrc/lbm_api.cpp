@@ -375,9 +375,6 @@ std::vector<unsigned char> cut_link_table(const RunDev &R, int prec)
     return out;
 }
 
-// Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD b mod 8), each XCD
-// with its own L2.  Reorder a run's row-major tile list so that XCD j receives a contiguous band of
-// tiles: the halo reads of neighbouring tiles then hit the same L2.
 // XCD-aware order of one run's tiles (row-major on entry): block b runs on XCD b mod 8, so each XCD
 // receives a contiguous band of tiles (their shared halos stay in one L2).  Within a band the tiles
 // for which first(tile) holds are dispatched first: the stream-and-collide tiles next to the cylinder,
