@@ -100,8 +100,10 @@ def main():
                     help="sweep: runs stepped as this many contiguous groups on streams of their own")
     ap.add_argument("--variants", default=None, metavar="L,T",
                     help="launch variant indices of k_lbm and k_thermal (instead of autotuning)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep"],
-                    help="c2: 1024x512 boiling channel (default); c3: the same at Re 30000; sweep: 64 uneven runs")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep", "big"],
+                    help="c2: 1024x512 boiling channel (default); c3: the same at Re 30000; sweep: 64 uneven runs; "
+                         "big: the Re 300 channel scaled by 8 (8192x4096, R 256), a state no cache holds, "
+                         "coupled from its first step")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
@@ -125,15 +127,20 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
         return
     from paper_1912_02018_amd import lbm
-    from paper_1912_02018_amd.config import config2, config3, sweep_configs
+    from paper_1912_02018_amd.config import config2, config3, sweep_configs, cylinder_config
 
     prec = PREC[args.precision]
     torch.cuda.set_device(0)
     if args.workload == "sweep":
         line = run_sweep(args, lbm, sweep_configs(64, 2018, prec), prec)
     else:
-        cfg = config2(prec) if args.workload == "c2" else config3(prec)
-        re = 300 if args.workload == "c2" else 30000
+        if args.workload == "big":
+            cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=prec, warmup=0)
+            if prec >= 2:
+                cfg = cfg.replace(rho_ref_shift=lbm.saturation(cfg)["rho_l"])
+        else:
+            cfg = config2(prec) if args.workload == "c2" else config3(prec)
+        re = 30000 if args.workload == "c3" else 300
         if args.skip_physical_warmup:
             cfg = cfg.replace(warmup_steps=0)
         workload = f"boiling-cylinder-{cfg.nx}x{cfg.ny}-R{cfg.cyl_r}-Re{re}-rk{cfg.rk_stages}-{args.precision}"
