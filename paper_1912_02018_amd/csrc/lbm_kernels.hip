@@ -121,7 +121,6 @@ __device__ inline Dual operator/(const Dual &a, const Dual &b)
 }
 __device__ inline Dual &operator+=(Dual &a, const Dual &b) { return a = a + b; }
 __device__ inline bool operator==(const Dual &a, const Dual &b) { return a.v == b.v; }
-__device__ inline bool operator!=(const Dual &a, const Dual &b) { return a.v != b.v; }
 __device__ inline bool operator<(const Dual &a, const Dual &b) { return a.v < b.v; }
 __device__ inline bool operator>(const Dual &a, const Dual &b) { return a.v > b.v; }
 template <> struct Ar<Dual> {
@@ -1461,16 +1460,16 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // stream+collide: FP32 and reduced-precision storage / FP64
 static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 512, 0}, {32, 8, 256, 0},
                                  {32, 8, 256, 6},  {64, 8, 512, 6},  {64, 8, 512, 7}};
-static const Variant kLbm64[] = {{32, 16, 256}, {16, 16, 256}};
-// temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage)
-// (64 x 32 with 512 threads: also with a register budget of 4 waves per SIMD, which gives it a
-// second workgroup per CU)
-static const Variant kTh32[] = {{64, 32, 512, 0}, {32, 32, 512, 0}, {64, 32, 1024, 0}, {32, 32, 256, 0}, {64, 32, 512, 4}};
-static const Variant kTh64[] = {{16, 16, 256}, {32, 16, 256}};
+static const Variant kLbm64[] = {{32, 16, 256, 0}, {16, 16, 256, 0}};
+// temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage); 64 x 32 with 512
+// threads also with a register budget of 4 waves per SIMD, which gives it a second workgroup per CU
+static const Variant kTh32[] = {{64, 32, 512, 0}, {32, 32, 512, 0}, {64, 32, 1024, 0}, {32, 32, 256, 0},
+                                {64, 32, 512, 4}};
+static const Variant kTh64[] = {{16, 16, 256, 0}, {32, 16, 256, 0}};
 // tangent precision (40-byte values): one small tile each (the RK4 temperature tile with its
 // 8-node halo stays within the 160 KB of LDS)
-static const Variant kTanLbm[] = {{16, 16, 256}};
-static const Variant kTanTh[] = {{16, 8, 256}};
+static const Variant kTanLbm[] = {{16, 16, 256, 0}};
+static const Variant kTanTh[] = {{16, 8, 256, 0}};
 
 int variant_count(int precision, int kernel)
 {
