@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
 // 40-byte values of a slot pair's windows would not fit the registers); slots, stages and the
 // stencils' grouping by weight class as in k_thermal, with the opposite-neighbour differences of a
 // single 5 x 5 window
-template <int TX, int TY, int NS> struct ThGeom1 {
+template <int TX, int TY, int NS> struct ThGeomTan {
     static constexpr int H = 2 * NS;
     // region of RX x RH positions stored with an odd row stride RW (the ring slots of a wavefront
     // are short row pieces a stride apart, which an even stride would put on few LDS banks)
@@ -1071,14 +1071,14 @@ template <int TX, int TY, int NS> struct ThGeom1 {
     static constexpr int NSLOT = count(1);
 };
 
-template <int TX, int TY, int NS> struct SlotTable1 {
-    unsigned short pos[ThGeom1<TX, TY, NS>::NSLOT];
+template <int TX, int TY, int NS> struct SlotTableTan {
+    unsigned short pos[ThGeomTan<TX, TY, NS>::NSLOT];
 };
 
-template <int TX, int TY, int NS> constexpr SlotTable1<TX, TY, NS> make_slots1()
+template <int TX, int TY, int NS> constexpr SlotTableTan<TX, TY, NS> make_slots_tan()
 {
-    using G = ThGeom1<TX, TY, NS>;
-    SlotTable1<TX, TY, NS> t{};
+    using G = ThGeomTan<TX, TY, NS>;
+    SlotTableTan<TX, TY, NS> t{};
     int r = 0;
     for (int y = 0; y < TY; ++y)
         for (int x = 0; x < TX; ++x) t.pos[r++] = (unsigned short)((G::H + y) * G::RW + G::H + x);
@@ -1095,10 +1095,10 @@ template <int TX, int TY, int NS> constexpr SlotTable1<TX, TY, NS> make_slots1()
     return t;
 }
 
-template <int TX, int TY, int NS> __constant__ const SlotTable1<TX, TY, NS> kSlots1 = make_slots1<TX, TY, NS>();
+template <int TX, int TY, int NS> __constant__ const SlotTableTan<TX, TY, NS> kSlotsTan = make_slots_tan<TX, TY, NS>();
 
-template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal1 {
-    using G = ThGeom1<TX, TY, NS>;
+template <typename C, int TX, int TY, int NS, int NT, bool PH> struct ThermalTan {
+    using G = ThGeomTan<TX, TY, NS>;
     static constexpr int H = G::H, RW = G::RW, RN = G::RN, TN = G::TN, NSLOT = G::NSLOT;
     static constexpr int ITER = (NSLOT + NT - 1) / NT;
 
@@ -1204,7 +1204,7 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH>
 __global__ __launch_bounds__(NT) void k_thermal_tan(const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt,
                                                 long long step)
 {
-    using Th = Thermal1<C, TX, TY, NS, NT, PH>;
+    using Th = ThermalTan<C, TX, TY, NS, NT, PH>;
     constexpr int H = Th::H, RX = Th::G::RX, RW = Th::RW, RH = Th::G::RH, TN = Th::TN, NSLOT = Th::NSLOT;
     constexpr int ITER = Th::ITER;
     __shared__ typename Th::Smem sm;
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(NT) void k_thermal_tan(const RunDev *__restrict__ r
 #pragma unroll
     for (int j = 0; j < ITER; ++j) {
         const int r = threadIdx.x + NT * j;
-        spos[j] = r < NSLOT ? (int)kSlots1<TX, TY, NS>.pos[r] : 0;
+        spos[j] = r < NSLOT ? (int)kSlotsTan<TX, TY, NS>.pos[r] : 0;
     }
 
     // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
