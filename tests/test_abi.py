@@ -93,3 +93,15 @@ def test_tangent_precision_sizing():
     with pytest.raises(lbm.LBMError):
         lbm.workspace_bytes([LBMConfig(nx=2048, ny=1024, cyl_x=600, cyl_y=512, cyl_r=420, alpha_T=0.01,
                                        precision=F64_TANGENT)])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for several it exits with status 2 and says why, before
+    touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
