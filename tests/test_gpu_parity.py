@@ -376,11 +376,12 @@ def test_profiled_steps_advance_like_steps(lbm_mod):
             a.profile_steps(bad)
 
 
-@pytest.mark.parametrize("precision", [FP32, FP64])
-def test_launch_variants_agree(lbm_mod, precision):
+@pytest.mark.parametrize("precision,rk", [(FP32, 4), (FP64, 4), (FP32, 2)])
+def test_launch_variants_agree(lbm_mod, precision, rk):
     """Every tile shape of both stencil kernels gives the same state bit for bit (the per-node
-    arithmetic does not depend on the tile); FP64 variants also match the oracle."""
-    cfg = cylinder_case(nx=100, ny=50, r=6, cx=30, precision=precision)
+    arithmetic does not depend on the tile, nor on where a temperature slot keeps T^n and its
+    accumulator); FP64 variants also match the oracle."""
+    cfg = cylinder_case(nx=100, ny=50, r=6, cx=30, precision=precision, rk=rk)
     ref_state = None
     probe = lbm_mod.Simulation(cfg)
     nl, nt = len(probe.variants(0)), len(probe.variants(1))
