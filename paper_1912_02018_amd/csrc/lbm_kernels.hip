@@ -874,6 +874,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
         return;
     }
     const Consts<C> K(R);
+    // a tile whose whole region lies inside the domain needs no ghost mapping, and one whose region
+    // misses the cylinder's box no solid test (same positions and kinds, fewer instructions)
+    const int rx0 = x0 - H, ry0 = y0 - H;
+    const bool interior = rx0 >= 0 && rx0 + RX <= nx && ry0 >= 0 && ry0 + RH <= ny;
+    const bool no_solid = R.cyl_r <= 0 || (interior && (rx0 + RX <= R.cyl_x - R.cyl_r || rx0 > R.cyl_x + R.cyl_r ||
+                                                       ry0 + RH <= R.cyl_y - R.cyl_r || ry0 > R.cyl_y + R.cyl_r));
 
     // LDS positions of this thread's slots, fetched from the constant table first so that their
     // latency overlaps the field loads
@@ -897,7 +903,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
             const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
             const int lx = n % RX, ly = n / RX;
             int rx, ry;
-            const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+            int kind = NODE;
+            if (interior) { rx = rx0 + lx; ry = ry0 + ly; }
+            else kind = map_pos<PH>(R, rx0 + lx, ry0 + ly, rx, ry);
             const unsigned idx = (unsigned)(ry * P + rx);
             if (kind == INLET_GHOST) inlet |= 1u << i;
             if (PH && kind == WALL_GHOST) wall |= 1u << i;
@@ -950,7 +958,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
         const int p = spos[j];
         const int lx = p % RW, ly = p / RW;
         int rx, ry;
-        const int kind = map_pos<PH>(R, x0 - H + lx, y0 - H + ly, rx, ry);
+        int kind = NODE;
+        if (interior) { rx = rx0 + lx; ry = ry0 + ly; }
+        else kind = map_pos<PH>(R, rx0 + lx, ry0 + ly, rx, ry);
         S.pos[j] = (unsigned)p;
         // the kind of a position depends on its column only, so both nodes of a slot share it
         if (kind == INLET_GHOST || kind == WALL_GHOST) {
@@ -958,7 +968,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
             continue;
         }
         const int ry1 = ry + 1 == ny ? 0 : ry + 1;
-        const unsigned hj = (solid_at(R, rx, ry) ? 1u : 0u) | (solid_at(R, rx, ry1) ? 2u : 0u);
+        const unsigned hj = no_solid ? 0u : (solid_at(R, rx, ry) ? 1u : 0u) | (solid_at(R, rx, ry1) ? 2u : 0u);
         S.hold |= hj << (2 * j);
         if (hj == 3u) continue;
         // an outlet ghost evaluates the operator at the last column of its row
