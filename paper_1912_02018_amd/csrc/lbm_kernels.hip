@@ -798,8 +798,9 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input.
     // The stage inputs alternate between two LDS arrays (Y and, once the stage invariants are
     // formed, the density's), so a slot writes its next input as soon as its k is known: one barrier
-    // per stage.  Stage 1 also copies the held positions into the second array.
-    template <int s>
+    // per stage.  Stage 1 also copies the held positions into the second array.  CLEAN: a tile with
+    // no held position (inside the domain, away from the cylinder), which skips the per-node checks.
+    template <int s, bool CLEAN>
     __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S, bool phase)
     {
         constexpr int CNT = G::count(s);
@@ -811,11 +812,11 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
             if (r >= CNT) continue;
             C kv[2] = {(C)0, (C)0};
             if (LAST_S1 && s == 1 && j == ITER - 1) { kv[0] = S.k1[0]; kv[1] = S.k1[1]; }
-            else if (S.evaluated(j)) rhs(Yin, K, S.cf[j < NCOEF ? j : 0], S.ev(j), phase, kv);
+            else if (CLEAN || S.evaluated(j)) rhs(Yin, K, S.cf[j < NCOEF ? j : 0], S.ev(j), phase, kv);
 #pragma unroll
             for (int n = 0; n < 2; ++n) {
                 const int o = S.own(j) + n * RW;
-                if ((S.hold >> (2 * j + n)) & 1u) {
+                if (!CLEAN && ((S.hold >> (2 * j + n)) & 1u)) {
                     if constexpr (s == 1) Yout[o] = Yin[o];
                     continue;
                 }
@@ -1045,11 +1046,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
     }
 
     __syncthreads();  // the density array is read by every slot's invariants before stage 1 reuses it
-    Th::template stage<1>(sm, K, S, phase);
-    Th::template stage<2>(sm, K, S, phase);
-    if constexpr (NS == 4) {
-        Th::template stage<3>(sm, K, S, phase);
-        Th::template stage<4>(sm, K, S, phase);
+    if (interior && no_solid) {
+        Th::template stage<1, true>(sm, K, S, phase);
+        Th::template stage<2, true>(sm, K, S, phase);
+        if constexpr (NS == 4) {
+            Th::template stage<3, true>(sm, K, S, phase);
+            Th::template stage<4, true>(sm, K, S, phase);
+        }
+    } else {
+        Th::template stage<1, false>(sm, K, S, phase);
+        Th::template stage<2, false>(sm, K, S, phase);
+        if constexpr (NS == 4) {
+            Th::template stage<3, false>(sm, K, S, phase);
+            Th::template stage<4, false>(sm, K, S, phase);
+        }
     }
 
     // the tile's slots come first
