@@ -758,6 +758,55 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
         C T0[NRK][2], acc[NRK][2];  // (!RK_IN_LDS)
     };
 
+    // The frozen fields rho, u and T^n on the region of the tile at (rx0, ry0) (ghost columns per the
+    // boundary conditions).  Every position of the thread: all loads are issued before the first LDS
+    // write (one memory round trip); ghost positions map to valid nodes, so every load is in bounds,
+    // and the ghost values replace the loaded ones afterwards.  INTERIOR: the region lies inside the
+    // domain (direct indexing, no ghosts).
+    template <bool INTERIOR>
+    __device__ static void load_region(Smem &sm, const RunDev &R, const Consts<C> &K, int rx0, int ry0, int pt)
+    {
+        constexpr int RX = G::RX, RH = G::RH, IL = (RX * RH + NT - 1) / NT;
+        const int P = R.pitch;
+        C lr[IL], lu[IL], lv[IL], lt[IL];
+        unsigned inlet = 0, wall = 0;
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
+            const int lx = n % RX, ly = n / RX;
+            int rx = rx0 + lx, ry = ry0 + ly;
+            if constexpr (!INTERIOR) {
+                const int kind = map_pos<PH>(R, rx0 + lx, ry0 + ly, rx, ry);
+                if (kind == INLET_GHOST) inlet |= 1u << i;
+                if (PH && kind == WALL_GHOST) wall |= 1u << i;
+            }
+            const unsigned idx = (unsigned)(ry * P + rx);
+            lr[i] = ld_at<C>(R.rho, idx);
+            lu[i] = ld_at<C>(R.ux, idx);
+            lv[i] = ld_at<C>(R.uy, idx);
+            lt[i] = ld_at<C>(R.T[pt], idx);
+        }
+#pragma unroll
+        for (int i = 0; i < IL; ++i) {
+            // (a thread past the region rewrites the last position with the value loaded for it,
+            // so that no load is sunk behind a branch)
+            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
+            const int p = (n / RX) * RW + n % RX;
+            if constexpr (INTERIOR) {
+                sm.rho[p] = lr[i];
+                sm.ux[p] = lu[i];
+                sm.uy[p] = lv[i];
+                sm.Y[p] = lt[i];
+            } else {
+                const bool w = (wall >> i) & 1u;
+                sm.rho[p] = w ? K.rho_w : lr[i];
+                sm.ux[p] = w ? (C)0 : lu[i];
+                sm.uy[p] = w ? (C)0 : lv[i];
+                sm.Y[p] = ((inlet >> i) & 1u) ? K.T_sat : (w ? K.T_w : lt[i]);
+            }
+        }
+    }
+
     // right-hand side L(Y) of eq. energy at both nodes of a slot with coefficients f, evaluated at
     // LDS positions c and c + RW of the stage input Y
     __device__ static void rhs(const C *Y, const Consts<C> &K, const Coef &f, int c, bool phase, C k[2])
@@ -892,42 +941,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
     }
 
     // the frozen fields and T^n on the whole region (ghost columns per the boundary conditions)
-    {
-        // every position of the thread: all loads are issued before the first LDS write (one memory
-        // round trip); ghost positions map to valid nodes, so every load is in bounds, and the
-        // ghost values replace the loaded ones afterwards
-        constexpr int IL = (RX * RH + NT - 1) / NT;
-        C lr[IL], lu[IL], lv[IL], lt[IL];
-        unsigned inlet = 0, wall = 0;
-#pragma unroll
-        for (int i = 0; i < IL; ++i) {
-            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
-            const int lx = n % RX, ly = n / RX;
-            int rx, ry;
-            int kind = NODE;
-            if (interior) { rx = rx0 + lx; ry = ry0 + ly; }
-            else kind = map_pos<PH>(R, rx0 + lx, ry0 + ly, rx, ry);
-            const unsigned idx = (unsigned)(ry * P + rx);
-            if (kind == INLET_GHOST) inlet |= 1u << i;
-            if (PH && kind == WALL_GHOST) wall |= 1u << i;
-            lr[i] = ld_at<C>(R.rho, idx);
-            lu[i] = ld_at<C>(R.ux, idx);
-            lv[i] = ld_at<C>(R.uy, idx);
-            lt[i] = ld_at<C>(R.T[pt], idx);
-        }
-#pragma unroll
-        for (int i = 0; i < IL; ++i) {
-            // (a thread past the region rewrites the last position with the value loaded for it,
-            // so that no load is sunk behind a branch)
-            const int n = min((int)threadIdx.x + NT * i, RX * RH - 1);
-            const int p = (n / RX) * RW + n % RX;
-            const bool w = (wall >> i) & 1u;
-            sm.rho[p] = w ? K.rho_w : lr[i];
-            sm.ux[p] = w ? (C)0 : lu[i];
-            sm.uy[p] = w ? (C)0 : lv[i];
-            sm.Y[p] = ((inlet >> i) & 1u) ? K.T_sat : (w ? K.T_w : lt[i]);
-        }
-    }
+    if (interior) Th::template load_region<true>(sm, R, K, rx0, ry0, pt);
+    else Th::template load_region<false>(sm, R, K, rx0, ry0, pt);
     __syncthreads();
 
     // slots and their stage-invariant coefficients:
