@@ -847,8 +847,8 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input.
     // The stage inputs alternate between two LDS arrays (Y and, once the stage invariants are
     // formed, the density's), so a slot writes its next input as soon as its k is known: one barrier
-    // per stage.  Stage 1 also copies the held positions into the second array.  CLEAN: a tile with
-    // no held position (inside the domain, away from the cylinder), which skips the per-node checks.
+    // per stage.  CLEAN: a tile with no held position (inside the domain, away from the cylinder),
+    // which skips the per-node hold test.
     template <int s, bool CLEAN>
     __device__ static void stage(Smem &sm, const Consts<C> &K, Slots &S, bool phase)
     {
@@ -865,11 +865,10 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
 #pragma unroll
             for (int n = 0; n < 2; ++n) {
                 const int o = S.own(j) + n * RW;
-                if (!CLEAN && ((S.hold >> (2 * j + n)) & 1u)) {
-                    if constexpr (s == 1) Yout[o] = Yin[o];
-                    continue;
-                }
-                const C k = kv[n];
+                // a held node takes k = 0: the update then rewrites its value unchanged (in stage 1
+                // that copies it into the second array), without a branch per node
+                C k = kv[n];
+                if constexpr (!CLEAN) k = ((S.hold >> (2 * j + n)) & 1u) ? (C)0 : k;
                 const int jr = RK_IN_LDS ? 0 : j;
                 C t0, a;
                 if constexpr (s == 1) {
