@@ -11,7 +11,9 @@
 //              central-moment collision reconstructed in closed form f* = M^-1 N(-u) k*.
 //              Writes f*, rho, u and the outlet history.  Bandwidth bound.
 //   k_thermal  all Runge-Kutta stages of the temperature equation for one tile in LDS, the tile
-//              carrying a halo of 2 nodes per stage so the stages never leave the CU.
+//              carrying a halo of 2 nodes per stage so the stages never leave the CU; positions
+//              are updated in vertically adjacent pairs that share their stencil rows
+//              (k_thermal_tan: the same step for the tangent precision, one position at a time).
 //   k_diag_*   FP64 mass and wall heat-flux reductions in a fixed order (bitwise reproducible).
 //   k_init     f* := f^eq(rho, u), outlet history, temperature from host-provided fields.
 // No MFMA: every kernel is a stencil or an elementwise map.  The 24-neighbour stencils are
