@@ -412,7 +412,9 @@ def run_single(args, lbm, cfg, prec, workload, re):
     progress(f"{workload}: warm-up")
     sim = lbm.Simulation(cfg)
     sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
-    choose_variants(args, sim, 20)      # launch variants timed on the coupled state (untimed)
+    # launch variants timed on the coupled state (untimed); small grids take more pseudo-steps per
+    # variant, which keeps the choice stable against run-to-run noise at little cost
+    choose_variants(args, sim, 100 if cfg.nx * cfg.ny <= (1 << 20) else 20)
     sim.step(args.warmup)
     ms, wall = timed_steps(torch, sim, args.steps)
     ms_step = ms / args.steps
