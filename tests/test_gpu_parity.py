@@ -193,19 +193,22 @@ def developed_state(lbm, cfg, steps):
     return sim
 
 
-@pytest.mark.parametrize("precision,tol,tol_u", [(FP64, TOL64, TOL64), (FP32, 2e-6, 2e-5)])
-def test_full_size_one_step(lbm_mod, precision, tol, tol_u):
-    """1024x512 boiling channel (bench launch configuration): after 200 coupled steps on the GPU
-    the oracle takes the GPU state and both advance one step."""
+@pytest.mark.parametrize("precision,tol,tol_u,rk", [(FP64, TOL64, TOL64, 4), (FP32, 2e-6, 2e-5, 4),
+                                                     (FP32, 2e-6, 2e-5, 2)])
+def test_full_size_one_step(lbm_mod, precision, tol, tol_u, rk):
+    """1024x512 boiling channel (bench launch configuration; RK2 too, the paper's scheme): after 200
+    coupled steps on the GPU the oracle takes the GPU state and both advance one step."""
     rl, rv = coex()
-    cfg = config2(precision).replace(warmup_steps=0, rho_l=rl, rho_v=rv)
-    sim = developed_state(lbm_mod, cfg, 200)
+    cfg = config2(precision).replace(warmup_steps=0, rho_l=rl, rho_v=rv, rk_stages=rk)
+    sim = lbm_mod.Simulation(cfg)
+    sim.autotune(5)  # the launch variants the bench would time
+    sim.step(200)
     fs, hist, T, step = sim.get_state()
     ref = oracle.Sim(cfg.replace(precision=FP64))
     ref.set_state(fs, hist, T, step)
     sim.step(1)
     ref.step(1)
-    compare(sim, ref, f"1024x512 one step from GPU state ({'fp64' if precision == FP64 else 'fp32'})",
+    compare(sim, ref, f"1024x512 RK{rk} one step from GPU state ({'fp64' if precision == FP64 else 'fp32'})",
             tol=tol, tol_u=tol_u, u_ref=cfg.u_in)
 
 
