@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -64,8 +65,21 @@ def measured_traffic(variant: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, budget_s: float):
-    """FP64 oracle (OpenMP over nodes) on the same workload, timed on a bounded number of steps."""
+    """FP64 oracle (OpenMP over nodes) on the same workload, timed on a bounded number of steps.
+    cores: the OpenMP threads the oracle runs with (OMP_NUM_THREADS, else the cores of this
+    process's affinity mask); the affinity mask's size is reported beside it."""
     import oracle
     from paper_1912_02018_amd.config import FP64
     c = cfg.replace(precision=FP64, warmup_steps=0)
@@ -77,9 +91,9 @@ def cpu_baseline(cfg, budget_s: float):
     t0 = time.perf_counter()
     sim.step(n)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(c.nx * c.ny * n / dt / 1e6, 4), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
+    affinity = len(os.sched_getaffinity(0))
+    return {"value": round(c.nx * c.ny * n / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle", "cpu_model": cpu_model(), "affinity_cores": affinity,
             "sample": f"{n} coupled FP64 steps of the {c.nx}x{c.ny} workload after 1 untimed step "
                       f"({dt:.1f} s)"}
 
@@ -91,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=sorted(PREC))
     ap.add_argument("--kernel-launches", type=int, default=200)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed windows of --steps steps each; the value is their median")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-physical-warmup", action="store_true",
@@ -167,11 +183,12 @@ def sweep_summary(args, lbm):
     stepped one after another (shorter timing than --workload sweep)."""
     from paper_1912_02018_amd.config import sweep_configs
     sub = argparse.Namespace(**vars(args))
-    sub.steps, sub.warmup, sub.kernel_launches, sub.variants = 1000, 100, 20, None
+    sub.steps, sub.warmup, sub.kernel_launches, sub.variants, sub.repeats = 1000, 100, 20, None, 3
     rec = run_sweep(sub, lbm, sweep_configs(64, 2018, PREC["f32"]), PREC["f32"])
     return {"workload": rec["config"]["workload"], "nodes": rec["config"]["nodes"], "mlups": rec["value"],
             "sequential_mlups": rec["sequential_mlups"], "ratio": rec["batched_over_sequential"],
-            "steps": sub.steps}
+            "steps": sub.steps, "timing": rec["timing"], "variants": rec["config"]["variants"],
+            "sequential_distinct_shapes_tuned": len(rec["sequential_variants"])}
 
 
 def reduced_storage_report(lbm, steps=1000):
@@ -186,6 +203,7 @@ def reduced_storage_report(lbm, steps=1000):
     rho_l = None
     cases = (("f64", "f64", None), ("f32", "f32", None), ("f16s_shift_1", "f16s", 1.0),
              ("f16s_shift_rho_l", "f16s", "rho_l"), ("bf16s_shift_rho_l", "bf16s", "rho_l"))
+    # (the storage shift defaults to rho_l; the literal f_i - w_i of rho_ref = 1 is the comparison)
     for label, pname, shift in cases:
         cfg = config3(PREC[pname])
         if shift == "rho_l":
@@ -322,6 +340,39 @@ def timed_steps(torch, sim, steps):
     return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
+def launch_period(cfgs) -> int:
+    """Period of the library's launch pattern once the runs are past warm-up: the buffers alternate
+    every step, and the Nu accumulation recurs every diag_every steps (lcm of 2 and those periods)."""
+    L = 2
+    for c in cfgs:
+        if c.diag_every > 0:
+            L = L * c.diag_every // math.gcd(L, c.diag_every)
+    return L
+
+
+def align(sim, period: int):
+    """Untimed steps up to the next multiple of the launch period, so that a timed window starts where
+    the library replays its captured period (graph launches, diagnostics included)."""
+    r = sim.step_count % period
+    if r:
+        sim.step(period - r)
+
+
+def timed_windows(torch, sim, steps, repeats, period):
+    """`repeats` windows of exactly `steps` steps, each starting at a multiple of the launch period and
+    bracketed by device synchronisations; returns the median window's milliseconds and wall-clock
+    seconds, and every window's milliseconds."""
+    reps, walls = [], []
+    for _ in range(max(1, repeats)):
+        align(sim, period)
+        ms, wall = timed_steps(torch, sim, steps)
+        reps.append(ms)
+        walls.append(wall)
+    order = sorted(range(len(reps)), key=lambda k: reps[k])
+    mid = order[len(order) // 2]
+    return reps[mid], walls[mid], reps
+
+
 def isolated_kernel_ms(torch, sim, launches):
     """Average duration of back-to-back launches of each kernel on an unchanging state (HIP events
     on the library's stream): the inputs stay cache-hot, so these run faster than in the step."""
@@ -340,14 +391,15 @@ def isolated_kernel_ms(torch, sim, launches):
 
 def timed_region_kernel_ms(sim, launches, ms_step):
     """Average duration of each kernel in the timed region: the timed step time (HIP events around the
-    graph-replayed steps, whose kernels run back to back) divided between k_lbm and k_thermal in the
-    proportion of their dispatch durations, measured by `launches` further steps right after the timed
-    region with every dispatch timed by its own start / stop HIP events.  Directly launched steps leave
-    gaps between the kernels, so their raw dispatch durations differ by a few percent from the
-    back-to-back ones; both are returned."""
+    graph-replayed steps, whose kernels run back to back) divided between k_lbm, k_thermal and the
+    diagnostic reductions in the proportion of their dispatch durations, measured by `launches`
+    further steps right after the timed region with every dispatch timed by its own start / stop HIP
+    events (the reductions by events around them, per step).  Directly launched steps leave gaps
+    between the kernels, so their raw dispatch durations differ by a few percent from the back-to-back
+    ones; both are returned."""
     disp = sim.profile_steps(launches)
-    share = ms_step / (disp[0] + disp[1])
-    return {0: disp[0] * share, 1: disp[1] * share}, {0: disp[0], 1: disp[1]}
+    share = ms_step / (disp[0] + disp[1] + disp[2])
+    return {0: disp[0] * share, 1: disp[1] * share}, {0: disp[0], 1: disp[1], "diag": disp[2]}
 
 
 def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload, ms_step):
@@ -372,7 +424,7 @@ def kernel_roofline(torch, sim, cfg, prec, nodes, launches, workload, ms_step):
     roof["kernel_ms"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in kt.items()}
     roof["timing"] = (f"timed-region step time split by the dispatch-event durations of {launches} further steps; "
                       "kernel_ms_dispatch: those raw durations (directly launched steps)")
-    roof["kernel_ms_dispatch"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in disp.items()}
+    roof["kernel_ms_dispatch"] = {KERNEL_NAMES.get(k, k): round(v, 5) for k, v in disp.items()}
     roof["kernel_ms_isolated"] = {KERNEL_NAMES[k]: round(v, 5) for k, v in isolated_kernel_ms(torch, sim, launches).items()}
     roof["kernel_hbm_gbs"] = {KERNEL_NAMES[k]: round(kernel_bytes_per_lup(k, prec) * nodes / (v * 1e-3) / 1e9, 1)
                               for k, v in kt.items()}
@@ -416,7 +468,7 @@ def run_single(args, lbm, cfg, prec, workload, re):
     # variant, which keeps the choice stable against run-to-run noise at little cost
     choose_variants(args, sim, 100 if cfg.nx * cfg.ny <= (1 << 20) else 20)
     sim.step(args.warmup)
-    ms, wall = timed_steps(torch, sim, args.steps)
+    ms, wall, reps = timed_windows(torch, sim, args.steps, args.repeats, launch_period([cfg]))
     ms_step = ms / args.steps
     nodes = cfg.nx * cfg.ny
     mlups = nodes / (ms_step * 1e-3) / 1e6
@@ -428,11 +480,13 @@ def run_single(args, lbm, cfg, prec, workload, re):
     line = base_line(args, prec, mlups, ms_step, {
         "workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r, "u_in": cfg.u_in, "Re": re,
         "rk_stages": cfg.rk_stages, "warmup_steps_untimed": cfg.warmup_steps + args.warmup,
-        "parallelism": "single-gpu",
+        "diag_every": cfg.diag_every, "parallelism": "single-gpu",
         "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]},
         "variants": [sim.get_variant(0), sim.get_variant(1)]})
     line["roofline"] = kernel_roofline(torch, sim, cfg, prec, nodes, args.kernel_launches, workload, ms_step)
     line["wall_s"] = round(wall, 3)
+    line["timing"] = {"repeats": len(reps), "ms_per_step_each": [round(r / args.steps, 6) for r in reps],
+                      "statistic": "median", "window_aligned_to_launch_period": launch_period([cfg])}
     line["diagnostics"] = {"mass": mass, "q_mean": q, "nu": nu}
     if not args.no_cpu_baseline:
         progress("cpu_baseline")
@@ -451,17 +505,23 @@ def run_sweep(args, lbm, cfgs, prec):
     groups = max(1, min(args.stream_groups, len(cfgs)))
     sim.set_stream_groups(groups)
     sim.step(args.warmup)
-    ms, wall = timed_steps(torch, sim, args.steps)
+    period = launch_period(cfgs)
+    ms, wall, reps = timed_windows(torch, sim, args.steps, args.repeats, period)
     ms_step = ms / args.steps
     batched = nodes / (ms_step * 1e-3) / 1e6
-    # sequential: each run alone on its own handle (same configuration, warm-up already passed)
-    seq_steps = max(10, args.steps // 10)
+    # sequential: each run alone on its own handle (same configuration, warm-up already passed), with
+    # launch variants tuned for its own shape (remembered per shape) and timed over one whole launch
+    # period (graph replay and its diagnostic step included), as the batched windows are
     seq_ms = 0.0
+    seq_var = {}
     for c in cfgs:
         one = lbm.Simulation(c.replace(warmup_steps=0))
         one.step(20)
-        t_ms, _ = timed_steps(torch, one, seq_steps)
-        seq_ms += t_ms / seq_steps
+        if not args.no_autotune:
+            seq_var[f"{c.nx}x{c.ny}r{c.cyl_r}"] = list(one.autotune(10, cached=True))
+        align(one, period)
+        t_ms, _ = timed_steps(torch, one, period)
+        seq_ms += t_ms / period
         one.close()
         del one
     sequential = nodes / (seq_ms * 1e-3) / 1e6
@@ -474,6 +534,10 @@ def run_sweep(args, lbm, cfgs, prec):
         "variants": [sim.get_variant(0), sim.get_variant(1)]})
     line["sequential_mlups"] = round(sequential, 1)
     line["batched_over_sequential"] = round(batched / sequential, 3)
+    line["sequential_variants"] = seq_var
+    line["timing"] = {"repeats": len(reps), "ms_per_step_each": [round(r / args.steps, 6) for r in reps],
+                      "statistic": "median", "window_aligned_to_launch_period": period,
+                      "sequential": f"one window of {period} steps per run, aligned, after 20 steps and its tuning"}
     line["roofline"] = kernel_roofline(torch, sim, cfgs[0], prec, nodes, max(10, args.kernel_launches // 10),
                                        f"boiling-sweep-{len(cfgs)}-runs-{args.precision}", ms_step)
     line["wall_s"] = round(wall, 3)

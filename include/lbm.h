@@ -57,11 +57,12 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_BF16S = 3, LBM_F64_TANGENT
 enum { LBM_TANGENTS = 4 };
 
 /* x boundaries; y is always periodic.  LBM_BC_INLET_OUTLET: Zou-He velocity inlet (u_in, 0) at
- * x = 0 and convective outlet (speed u_in) at x = nx-1 (Sec. IV A).  LBM_BC_WALL_OUTLET: heated
+ * x = 0 and convective outlet (speed per outlet_kind, default u_in) at x = nx-1 (Sec. IV A).  LBM_BC_WALL_OUTLET: heated
  * no-slip wall at x = -1/2 (halfway bounce-back; T = T_w, and behind it rho_wall, u = 0 like the
  * cylinder's solid nodes) with the same convective outlet: the Stefan problem (Sec. III E).  The
  * default state of a wall run is at rest.  FP64 and FP32 only. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_INLET_OUTLET = 1, LBM_BC_WALL_OUTLET = 2 };
+enum { LBM_OUTLET_U_IN = 0, LBM_OUTLET_LOCAL = 1 };
 
 typedef struct {
     int32_t nx, ny;         /* grid (>= 4 each) */
@@ -87,13 +88,22 @@ typedef struct {
     double cv;              /* specific heat at constant volume */
     int32_t precision;      /* LBM_FP64 ... LBM_F64_TANGENT; all runs of a handle share it */
     int32_t check_every;    /* > 0: lbm_step checks the state for non-finite values */
-    double rho_ref_shift;   /* reduced-precision storage offset rho_ref (f_i - w_i rho_ref) */
+    double rho_ref_shift;   /* reduced-precision storage offset rho_ref (f_i - w_i rho_ref); <= 0 selects
+                               rho_l, which keeps the liquid's populations near zero (rho_ref = 1 is the
+                               literal f_i - w_i) */
     double nu_vapor;        /* > 0: phase-dependent viscosity: nu is the liquid value, nu_vapor the
                                vapour's, linear in rho between rho_v and rho_l (constant outside);
                                <= 0: nu everywhere.  FP64 and FP32 only. */
     double alpha_vapor;     /* > 0: phase-dependent thermal diffusivity, likewise with alpha_T the
                                liquid value; lambda = rho c_v alpha(rho) in the energy equation and
                                lambda_v = rho_v c_v alpha_vapor in Nu.  <= 0: alpha_T everywhere. */
+    int32_t outlet_kind;    /* convection speed U of the convective outlet (Sec. IV A):
+                               LBM_OUTLET_U_IN: U = u_in;
+                               LBM_OUTLET_LOCAL: U = max(0, x velocity of the outlet node's
+                               post-collision populations of the previous step), the local outflow
+                               speed (lets liquid displaced by growing vapour leave a closed-inlet
+                               domain such as the heated wall's).  FP64 and FP32 only. */
+    int32_t pad_;           /* reserved, 0 */
 } lbm_config;
 
 /* Bytes of device workspace needed for n_runs runs (cfgs[0..n_runs-1]); 0 on invalid input. */
@@ -209,8 +219,10 @@ int lbm_autotune(lbm_handle *h, int launches, int *best);
  * start / stop events of their own dispatches, so the durations are those inside the running
  * step sequence (caches as a step leaves them), not of repeated isolated launches.  Writes the
  * mean milliseconds per dispatch to kernel_ms[0] (k_lbm) and kernel_ms[1] (k_thermal; 0 if no
- * step advanced the temperature).  Synchronises the stream.  The state advances exactly as with
- * lbm_step.  Errors: LBM_EINVAL (NULL handle or kernel_ms, count out of range), LBM_EDEVICE. */
+ * step advanced the temperature), and to kernel_ms[2] the time of the diagnostic reductions
+ * (heat flux, Nu, mass; events around them) per step, averaged over all n_steps steps.
+ * Synchronises the stream.  The state advances exactly as with lbm_step.  Errors: LBM_EINVAL
+ * (NULL handle or kernel_ms, count out of range), LBM_EDEVICE. */
 #define LBM_MAX_PROFILE_STEPS 4096
 int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms);
 

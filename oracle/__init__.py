@@ -28,7 +28,7 @@ PARAM_FIELDS = [
     ("G", C.c_double), ("sigma", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
     ("rho_gref", C.c_double), ("rho_l", C.c_double), ("rho_v", C.c_double),
     ("rho_wall", C.c_double), ("u_in", C.c_double), ("alpha_T", C.c_double), ("cv", C.c_double),
-    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double),
+    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double), ("outlet_kind", C.c_int32),
 ]
 
 
@@ -107,6 +107,8 @@ def lib():
         L.orc_iso_lap_periodic.argtypes = [i, i, dp, dp]
         L.orc_stencil_weight.argtypes = [i]
         L.orc_stencil_weight.restype = d
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = i
         _lib = L
     return _lib
 
@@ -227,6 +229,11 @@ def iso_lap_periodic(a):
     out = np.zeros_like(a)
     lib().orc_iso_lap_periodic(nx, ny, _dptr(a), _dptr(out))
     return out
+
+
+def threads() -> int:
+    """Threads of the oracle's OpenMP loops over nodes."""
+    return int(lib().orc_threads())
 
 
 def stencil_weight(e2: int) -> float:

@@ -33,6 +33,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------------------------ */
 /* Parameters (a struct of the oracle's own)                                                   */
@@ -60,6 +63,7 @@ typedef struct {
     double cv;            /* specific heat at constant volume */
     double nu_vapor;      /* vapour kinematic viscosity; <= 0: nu in both phases */
     double alpha_vapor;   /* vapour thermal diffusivity; <= 0: alpha_T in both phases */
+    int32_t outlet_kind;  /* speed of the convective outlet: 0 u_in; 1 the local outflow velocity */
 } orc_params;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -644,6 +648,24 @@ double orc_convective(double U, double f_old_last, double f_new_prev)
     return (f_old_last + U * f_new_prev) / (1.0 + U);
 }
 
+/* Convection speed U of the outlet in row y (reading of the convective condition, whose speed the
+ * paper leaves open): the inlet velocity, or the local outflow velocity -- the x velocity of the
+ * outlet node's post-collision populations of the previous step, u = sum f*_i c_ix / sum f*_i,
+ * taken as 0 where the fluid flows back in (a negative speed would make the upwind update unstable). */
+static double outlet_speed(const orc_sim *s, int y)
+{
+    if (s->p.outlet_kind != 1) return s->p.u_in;
+    int k = y * s->nx + s->nx - 1;
+    double m = 0.0, jx = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        double fi = s->fstar[(size_t)i * s->n + k];
+        m += fi;
+        jx += fi * CX[i];
+    }
+    double u = jx / m;
+    return u > 0.0 ? u : 0.0;
+}
+
 /* fill s->f (post-streaming populations) for every fluid node; returns the new outlet history */
 static void stream_all(orc_sim *s, double *new_hist)
 {
@@ -664,10 +686,11 @@ static void stream_all(orc_sim *s, double *new_hist)
                 f[i] = pull_interior(s, i, x, y);
             }
             if (s->p.bc_x != 0 && x == nx - 1) {
+                double U = outlet_speed(s, y);
                 for (int m = 0; m < 3; ++m) {
                     int i = OUT_DIRS[m];
                     double prev_col = pull_interior(s, i, nx - 2, y);
-                    f[i] = orc_convective(s->p.u_in, s->hist[m * ny + y], prev_col);
+                    f[i] = orc_convective(U, s->hist[m * ny + y], prev_col);
                 }
             }
             if (s->p.bc_x == 1 && x == 0) orc_zou_he(s->p.u_in, f);
@@ -1057,3 +1080,13 @@ void orc_iso_lap_periodic(int nx, int ny, const double *a, double *lap)
 }
 
 double orc_stencil_weight(int e2) { return stencil_w(e2); }
+
+/* number of threads the OpenMP loops over nodes use */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

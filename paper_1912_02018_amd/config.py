@@ -21,6 +21,7 @@ PRECISION_NAMES = {FP64: "f64", FP32: "f32", FP16S: "f16-store", BF16S: "bf16-st
 # parameter directions of the tangent precision (order of lbm_nu_tangent)
 TANGENT_PARAMS = ("dTr_wall", "u_in", "acentric", "tau")
 BC_PERIODIC, BC_INLET_OUTLET, BC_WALL_OUTLET = 0, 1, 2
+OUTLET_U_IN, OUTLET_LOCAL = 0, 1
 
 
 @dataclass
@@ -55,9 +56,11 @@ class LBMConfig:
     cv: float = 11.0
     precision: int = FP64
     check_every: int = 0         # > 0: lbm_step reports non-finite state
-    rho_ref_shift: float = 1.0   # reduced-precision storage holds f_i - w_i * rho_ref_shift
+    rho_ref_shift: float = 0.0   # reduced-precision storage holds f_i - w_i * rho_ref_shift; <= 0: rho_l
     nu_vapor: float = 0.0        # > 0: vapour viscosity (nu is then the liquid's), linear in density between
     alpha_vapor: float = 0.0     # > 0: vapour thermal diffusivity (alpha_T the liquid's), same interpolation
+    outlet_kind: int = 0         # convective-outlet speed: 0 u_in, 1 local outflow velocity of the outlet node
+    pad_: int = 0
 
     def replace(self, **kw) -> "LBMConfig":
         return dataclasses.replace(self, **kw)
@@ -91,15 +94,16 @@ def cylinder_config(nx: int, ny: int, radius: int, cx: int, re: float, u_in: flo
 
 def config2(precision: int = FP32) -> LBMConfig:
     """Forced-convection boiling: 1024x512 channel, R = 32 at x = 256, u_in = 0.02, Re = 300,
-    superheat 0.1 T_c, gravity -1e-5 along x, RK4, 3000 warm-up steps."""
+    superheat 0.1 T_c, gravity -1e-5 along x, RK4, 3000 warm-up steps, wall Nu logged every 20
+    steps."""
     return cylinder_config(1024, 512, 32, 256, re=300.0, u_in=0.02, dTr_wall=0.1,
-                           precision=precision)
+                           precision=precision, diag_every=20)
 
 
 def config3(precision: int = FP16S) -> LBMConfig:
     """config2 at Re = 30000 with u_in = 0.05."""
     return cylinder_config(1024, 512, 32, 256, re=30000.0, u_in=0.05, dTr_wall=0.1,
-                           precision=precision)
+                           precision=precision, diag_every=20)
 
 
 def config5(precision: int = FP32) -> LBMConfig:

@@ -216,8 +216,12 @@ int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
         if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET && k.bc_x != LBM_BC_WALL_OUTLET)
             return fail(h, LBM_EINVAL, "run %d: bad bc_x", r);
         if (k.precision < 0 || k.precision > 4) return fail(h, LBM_EINVAL, "run %d: bad precision", r);
-        if (k.precision >= 2 && (k.nu_vapor > 0 || k.alpha_vapor > 0 || k.bc_x == LBM_BC_WALL_OUTLET))
-            return fail(h, LBM_EINVAL, "run %d: phase-dependent transport and the heated wall need FP64 or FP32", r);
+        if (k.outlet_kind != LBM_OUTLET_U_IN && k.outlet_kind != LBM_OUTLET_LOCAL)
+            return fail(h, LBM_EINVAL, "run %d: bad outlet_kind", r);
+        if (k.precision >= 2 && (k.nu_vapor > 0 || k.alpha_vapor > 0 || k.bc_x == LBM_BC_WALL_OUTLET ||
+                                 k.outlet_kind != LBM_OUTLET_U_IN))
+            return fail(h, LBM_EINVAL,
+                        "run %d: phase-dependent transport, the heated wall and the local outlet speed need FP64 or FP32", r);
         if (k.precision == 4 && probe_count(k.cyl_r) > lbm::kMaxTangentProbes)
             return fail(h, LBM_EINVAL, "run %d: cylinder too large for the tangent precision", r);
         if (k.precision != c[0].precision) return fail(h, LBM_EINVAL, "all runs must share one precision");
@@ -562,11 +566,12 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
         R.eos_a = k.eos_a; R.eos_b = k.eos_b; R.eos_R = k.eos_R;
         R.u_in = k.u_in; R.alpha = k.alpha_T; R.cv = k.cv;
         R.phase_props = (k.nu_vapor > 0 || k.alpha_vapor > 0) ? 1 : 0;
-        h->phase |= R.phase_props != 0 || R.bc_x == LBM_BC_WALL_OUTLET;
+        R.outlet_kind = k.outlet_kind;
+        h->phase |= R.phase_props != 0 || R.bc_x == LBM_BC_WALL_OUTLET || R.outlet_kind != LBM_OUTLET_U_IN;
         R.nu_l = k.nu;
         R.nu_v = k.nu_vapor > 0 ? k.nu_vapor : k.nu;
         R.alpha_v = k.alpha_vapor > 0 ? k.alpha_vapor : k.alpha_T;
-        R.shift = prec >= 2 ? k.rho_ref_shift : 0.0;
+        R.shift = prec >= 2 ? (k.rho_ref_shift > 0 ? k.rho_ref_shift : rl) : 0.0;
         R.inv_sqrt_Tc = 1.0 / std::sqrt(R.Tc);
         R.psi_scale = 2.0 / (R.G * (1.0 / 3.0));
         R.dphi_A = -R.kappa * (1.0 + R.kappa) / std::sqrt(R.Tc);
@@ -689,27 +694,35 @@ static int set_fields_impl(lbm_handle *h, int run, const double *rho, const doub
     return LBM_OK;
 }
 
-// Enqueue the launches of one step (no host synchronisation).  tm (optional, two entries): events
-// of the k_lbm and the k_thermal dispatch; *thermal_ran tells whether the second was launched.
-static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *thermal_ran = nullptr)
+// Enqueue the launches of one step (no host synchronisation).  tm (optional, three entries): events
+// of the k_lbm dispatch, of the k_thermal dispatch and around the step's diagnostic reductions;
+// *thermal_ran / *diag_ran tell whether the latter two were launched.
+static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *thermal_ran = nullptr,
+                        bool *diag_ran = nullptr)
 {
     HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm, h->n_lbm, h->pf, h->pt, h->ph,
                               h->step, h->stream, tm));
-    bool thermal = false;
+    bool thermal = false, diag = false;
     for (int r = 0; r < h->n_runs; ++r) {
         const lbm_config &k = h->cfgs[r];
         const bool fon = h->step >= k.warmup_steps;
         const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
         const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
-        if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, h->stream));
+        if (acc || chk) {
+            if (tm && !diag) HIPCHK(h, hipEventRecord(tm[2].start, h->stream));
+            diag = true;
+            HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, h->stream));
+        }
         thermal |= fon && k.rk_stages > 0;
     }
+    if (tm && diag) HIPCHK(h, hipEventRecord(tm[2].stop, h->stream));
     if (thermal) {
         HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
                                       h->stream, tm ? tm + 1 : nullptr));
         h->pt ^= 1;
     }
     if (thermal_ran) *thermal_ran = thermal;
+    if (diag_ran) *diag_ran = diag;
     h->pf ^= 1;
     h->ph ^= 1;
     h->step += 1;
@@ -1197,32 +1210,35 @@ int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms)
     if (n_steps < 1 || n_steps > LBM_MAX_PROFILE_STEPS)
         return fail(h, LBM_EINVAL, "profiled step count %d outside [1, %d]", n_steps, LBM_MAX_PROFILE_STEPS);
     EventPool pool;
-    pool.ev.reserve((size_t)4 * n_steps);
-    for (int k = 0; k < 4 * n_steps; ++k) {
+    pool.ev.reserve((size_t)6 * n_steps);
+    for (int k = 0; k < 6 * n_steps; ++k) {
         hipEvent_t e;
         HIPCHK(h, hipEventCreate(&e));
         pool.ev.push_back(e);
     }
-    std::vector<char> ran((size_t)n_steps, 0);
+    std::vector<char> ran((size_t)2 * n_steps, 0);
     for (int s = 0; s < n_steps; ++s) {
-        const lbm::Timing tm[2] = {{pool.ev[4 * s], pool.ev[4 * s + 1]}, {pool.ev[4 * s + 2], pool.ev[4 * s + 3]}};
-        bool th = false;
-        const int rc = enqueue_step(h, tm, &th);
+        const lbm::Timing tm[3] = {{pool.ev[6 * s], pool.ev[6 * s + 1]}, {pool.ev[6 * s + 2], pool.ev[6 * s + 3]},
+                                   {pool.ev[6 * s + 4], pool.ev[6 * s + 5]}};
+        bool th = false, dg = false;
+        const int rc = enqueue_step(h, tm, &th, &dg);
         if (rc) return rc;
-        ran[s] = th;
+        ran[2 * s] = th;
+        ran[2 * s + 1] = dg;
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    double sum[2] = {0, 0};
+    double sum[3] = {0, 0, 0};
     int cnt[2] = {0, 0};
     for (int s = 0; s < n_steps; ++s)
-        for (int k = 0; k < 2; ++k) {
-            if (k == 1 && !ran[s]) continue;
+        for (int k = 0; k < 3; ++k) {
+            if (k >= 1 && !ran[2 * s + (k - 1)]) continue;
             float ms = 0;
-            HIPCHK(h, hipEventElapsedTime(&ms, pool.ev[4 * s + 2 * k], pool.ev[4 * s + 2 * k + 1]));
+            HIPCHK(h, hipEventElapsedTime(&ms, pool.ev[6 * s + 2 * k], pool.ev[6 * s + 2 * k + 1]));
             sum[k] += ms;
-            cnt[k] += 1;
+            if (k < 2) cnt[k] += 1;
         }
     for (int k = 0; k < 2; ++k) kernel_ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+    kernel_ms[2] = sum[2] / n_steps;
     return LBM_OK;
 }
 

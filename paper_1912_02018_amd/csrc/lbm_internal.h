@@ -34,7 +34,8 @@ struct RunDev {
     double u_in, alpha, cv, shift;
     // phase-dependent transport (phase_props != 0): nu and alpha linear in rho between the vapour
     // (rho_v) and liquid (rho_l) values, held outside; alpha above is then the liquid value
-    int phase_props, pad1;
+    int phase_props;
+    int outlet_kind;          // convective-outlet speed: 0 u_in, 1 local outflow velocity (extended launch)
     double nu_l, nu_v, alpha_v, inv_drho;   // inv_drho = 1 / (rho_l - rho_v)
     // derived on the host: 1/sqrt(Tc), 2/(G cs^2), phi'(T) = dphi_A/sqrt(T) + dphi_B, 1/cv
     double inv_sqrt_Tc, psi_scale, dphi_A, dphi_B, inv_cv;

@@ -393,16 +393,32 @@ __device__ inline void fix_near(const RunDev &R, const Consts<C> &K, const char 
 }
 
 // Velocity inlet at x = 0 and convective outlet at x = nx - 1 (the heated wall's bounce-back is
-// part of the plain pulls).
-template <typename S, typename C>
-__device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, gp<const C> hin, int x, int y, C f[9])
+// part of the plain pulls).  EXT: the launch carries the extended features, among them the outlet
+// speed taken from the local outflow.
+template <typename S, typename C, bool EXT = true>
+__device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, const char *fin, gp<const C> hin, int x, int y,
+                                  C f[9])
 {
     const int nx = R.nx, ny = R.ny;
     if (x == nx - 1) {
         // convective outflow: f^{n+1}(N) = (f^n(N) + U f^{n+1}(N-1)) / (1 + U), i in {2,6,8}.  The
         // plain pulls of column N clamp their x source to N, so f[2], f[6], f[8] already hold
         // f*_2(N, y), f*_6(N, y + 1), f*_8(N, y - 1): the populations that stream into N - 1.
-        const C U = K.u_in;
+        C U = K.u_in;
+        if (EXT && R.outlet_kind == 1) {
+            // local outflow speed: x velocity of the node's own post-collision populations (the
+            // previous time level), none where the flow turns back in
+            const unsigned P = R.pitch, plane = (unsigned)R.ny * P;
+            C m = 0, jx = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const C fi = ldf<S, C>(fin, plane, P, i, x, y, K);
+                m = m + fi;
+                jx = jx + (C)cx_of(i) * fi;
+            }
+            U = jx / m;
+            U = U > (C)0 ? U : (C)0;
+        }
         const C inv = Ar<C>::rcp((C)1 + U);
         const C p2 = f[2], p6 = f[6], p8 = f[8];
         f[2] = (hin[0 * ny + y] + U * p2) * inv;
@@ -420,12 +436,12 @@ __device__ inline void apply_x_bc(const RunDev &R, const Consts<C> &K, gp<const 
 }
 
 // Corrections of the plain pulls f of a node next to the cylinder or on an inlet / outlet column.
-template <typename S, typename C>
+template <typename S, typename C, bool EXT = true>
 __device__ inline void fix_special(const RunDev &R, const Consts<C> &K, const char *fin, const void *hin, int x, int y,
                                    C f[9])
 {
     if (near_cylinder(R, x, y)) fix_near<S, C>(R, K, fin, x, y, f);
-    if (R.bc_x != 0 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C>(R, K, gin<C>(hin), x, y, f);
+    if (R.bc_x != 0 && (x == 0 || x == R.nx - 1)) apply_x_bc<S, C, EXT>(R, K, fin, gin<C>(hin), x, y, f);
 }
 
 // An index the optimiser cannot re-associate with the constant offsets added to it afterwards,
@@ -545,7 +561,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
         } else {
             C *f = fv[j];
             if (near_cylinder(R, rx, ry) || (R.bc_x != 0 && (rx == 0 || rx == nx - 1)))
-                fix_special<S, C>(R, K, fin, R.hist[ph], rx, ry, f);
+                fix_special<S, C, PH>(R, K, fin, R.hist[ph], rx, ry, f);
             rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
             T = ((inlet >> j) & 1u) ? K.T_sat : Tv[j];
             if (own) {

@@ -29,7 +29,7 @@ _CONFIG_FIELDS = [
     ("rho_gref", C.c_double), ("rho_l", C.c_double), ("rho_v", C.c_double),
     ("rho_wall", C.c_double), ("u_in", C.c_double), ("alpha_T", C.c_double), ("cv", C.c_double),
     ("precision", C.c_int32), ("check_every", C.c_int32), ("rho_ref_shift", C.c_double),
-    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double),
+    ("nu_vapor", C.c_double), ("alpha_vapor", C.c_double), ("outlet_kind", C.c_int32), ("pad_", C.c_int32),
 ]
 
 EXPORTED = [
@@ -197,10 +197,11 @@ class Simulation:
 
     def profile_steps(self, n: int):
         """Advance n steps with each k_lbm / k_thermal dispatch timed by its own start / stop
-        events; returns their mean durations in ms (k_lbm, k_thermal)."""
-        out = (C.c_double * 2)()
+        events; returns their mean durations in ms (k_lbm, k_thermal) and the diagnostic
+        reductions' time per step (ms, averaged over the n steps)."""
+        out = (C.c_double * 3)()
         self._check(self._L.lbm_profile_steps(self.h, int(n), out))
-        return out[0], out[1]
+        return out[0], out[1], out[2]
 
     def variants(self, kernel: int):
         """(tx, ty, threads, min_waves) of every launch variant of a kernel (0 k_lbm, 1 k_thermal);

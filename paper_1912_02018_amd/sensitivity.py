@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import lbm
-from .config import F64_TANGENT, FP64, TANGENT_PARAMS, LBMConfig
+from .config import F64_TANGENT, TANGENT_PARAMS, LBMConfig
 
 __all__ = ["TANGENT_PARAMS", "params_of", "with_params", "hold_coexistence",
            "nu_average_and_gradient", "NuTimeAverage"]
@@ -36,15 +36,12 @@ def with_params(base: LBMConfig, theta) -> LBMConfig:
 
 
 def hold_coexistence(cfg: LBMConfig) -> LBMConfig:
-    """``cfg`` with explicit rho_l, rho_v: the Maxwell densities the library derives for it."""
+    """``cfg`` with explicit rho_l, rho_v: the Maxwell densities the library derives for it (a host
+    computation, no device needed)."""
     if cfg.rho_l > 0 and cfg.rho_v > 0:
         return cfg
-    probe = lbm.Simulation(cfg.replace(nx=8, ny=8, bc_x=0, cyl_r=0, rk_stages=0, precision=FP64))
-    try:
-        d = probe.derived()
-    finally:
-        probe.close()
-    return cfg.replace(rho_l=d["rho_l"], rho_v=d["rho_v"])
+    sat = lbm.saturation(cfg)
+    return cfg.replace(rho_l=sat["rho_l"], rho_v=sat["rho_v"])
 
 
 def nu_average_and_gradient(cfg: LBMConfig, steps: int, average_from: int = 0):

@@ -302,18 +302,15 @@ def test_fp32_error_after_1000_steps(lbm_mod):
 # Reduced-precision storage (FP32 compute, populations stored as f_i - w_i rho_ref in FP16 or BF16)
 # after 1000 steps of a 256x128 channel (R 8, no warm-up) against the FP64 oracle.  Storage rounding
 # has relative spacing 2^-11 (FP16) or 2^-8 (BF16) on f_i - w_i rho_ref; with rho_ref = rho_l the
-# liquid's populations keep most of their bits, with rho_ref = 1 (f_i - w_i) they do not.  The bounds
-# are about three times the errors measured on MI355X (rho, u, T: max-norm relative over fluid nodes,
-# u relative to max(|u|, u_in)); Nu (relative) samples a thin layer at the wall and moves by a few
-# times between builds that only reorder FP32 operations, so its bound is about ten times.
-STORAGE_BOUNDS = {
-    # (Re, precision, shift): (rho, u, T, Nu)
-    (30000.0, "f16", "rho_l"): (1.5e-3, 1.5e-2, 2e-3, 3e-4),
-    (30000.0, "f16", "one"): (4e-2, 2e-1, 4e-2, 5e-3),
-    (30000.0, "bf16", "rho_l"): (2e-2, 1.5e-1, 2.5e-2, 2.5e-2),
-    (300.0, "f16", "rho_l"): (7e-4, 6e-3, 6e-4, 3e-4),
-    (300.0, "bf16", "rho_l"): (2e-2, 1.2e-1, 1.5e-2, 4e-2),
-}
+# liquid's populations keep most of their bits, with rho_ref = 1 (f_i - w_i) they do not.
+# Accuracy target of a usable reduced-storage run (max-norm relative over fluid nodes; u relative to
+# max(|u|, u_in); Nu relative): rho and T within 1e-3, u within 1e-2, Nu within 1e-3.  FP16 storage
+# shifted by w_i rho_l must meet it at both Reynolds numbers.  FP16 with the literal shift w_i and
+# BF16 storage do not (measured on MI355X: FP16 / w_i rho 1.1e-2 and u 4.7e-2 at Re 30000; BF16 /
+# w_i rho_l rho 6.4e-3 and u 4.4e-2 at Re 30000, 5.7e-3 and 4.1e-2 at Re 300): their errors are
+# reported and only held below a sanity ceiling of 0.2.
+STORAGE_TARGET = (1e-3, 1e-2, 1e-3, 1e-3)       # rho, u, T, Nu
+STORAGE_CASES = [("f16", "rho_l"), ("f16", "one"), ("bf16", "rho_l")]
 
 
 @pytest.mark.parametrize("re,u_in", [(30000.0, 0.05), (300.0, 0.02)])
@@ -328,23 +325,26 @@ def test_reduced_precision_storage_error_bounds(lbm_mod, re, u_in):
     fl = o["mask"] == 0
     nu0 = ref.wall_heat_flux()[1]
     errs = {}
-    for (r, pname, shift), bounds in STORAGE_BOUNDS.items():
-        if r != re:
-            continue
+    for pname, shift in STORAGE_CASES:
         prec = FP16S if pname == "f16" else BF16S
-        sim = lbm_mod.Simulation(base.replace(precision=prec, rho_ref_shift=rl if shift == "rho_l" else 1.0))
+        # the default shift (rho_ref_shift <= 0) is rho_l
+        sim = lbm_mod.Simulation(base.replace(precision=prec, rho_ref_shift=0.0 if shift == "rho_l" else 1.0))
         sim.step(1000)
         g = sim.fields()
         du = np.hypot(g["ux"] - o["ux"], g["uy"] - o["uy"])[fl].max()
         e = (rel(g["rho"][fl], o["rho"][fl]), float(du / max(np.hypot(o["ux"], o["uy"])[fl].max(), u_in)),
              rel(g["T"][fl], o["T"][fl]), abs(sim.wall_heat_flux()[1] / nu0 - 1.0))
         errs[(pname, shift)] = e
-        print(f"Re {re:g} {pname} shift {shift}: rho {e[0]:.2e} u {e[1]:.2e} T {e[2]:.2e} Nu {e[3]:.2e}", flush=True)
-        for name, v, b in zip(("rho", "u", "T", "Nu"), e, bounds):
-            assert v <= b, (re, pname, shift, name, v, b)
-    if ("f16", "one") in errs:
-        # shifting by w_i rho_l rather than w_i keeps the liquid's precision
-        assert errs[("f16", "rho_l")][0] * 5 <= errs[("f16", "one")][0]
+        meets = all(v <= t for v, t in zip(e, STORAGE_TARGET))
+        print(f"Re {re:g} {pname} shift {shift}: rho {e[0]:.2e} u {e[1]:.2e} T {e[2]:.2e} Nu {e[3]:.2e} "
+              f"({'meets' if meets else 'misses'} the accuracy target)", flush=True)
+        if (pname, shift) == ("f16", "rho_l"):
+            for name, v, b in zip(("rho", "u", "T", "Nu"), e, STORAGE_TARGET):
+                assert v <= b, (re, pname, shift, name, v, b)
+        else:
+            assert all(np.isfinite(v) and v <= 0.2 for v in e), (re, pname, shift, e)
+    # shifting by w_i rho_l rather than w_i keeps the liquid's precision
+    assert errs[("f16", "rho_l")][0] * 5 <= errs[("f16", "one")][0]
 
 
 def test_graph_replay_matches_eager_bitwise(lbm_mod):
@@ -364,7 +364,8 @@ def test_graph_replay_matches_eager_bitwise(lbm_mod):
 
 def test_profiled_steps_advance_like_steps(lbm_mod):
     """lbm_profile_steps advances the state exactly as lbm_step (bit for bit) and reports a
-    positive mean duration for both kernels; out-of-range counts are rejected."""
+    positive mean duration for both kernels and for the diagnostic reductions (every 10 steps);
+    out-of-range counts are rejected."""
     cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32)
     a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
     a.step(10)
@@ -373,7 +374,7 @@ def test_profiled_steps_advance_like_steps(lbm_mod):
     b.step(37)
     assert a.step_count == b.step_count == 47
     assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
-    assert 0 < ms[0] < 100 and 0 < ms[1] < 100, ms
+    assert 0 < ms[0] < 100 and 0 < ms[1] < 100 and 0 < ms[2] < 100, ms
     for bad in (0, 4097):
         with pytest.raises(lbm_mod.LBMError):
             a.profile_steps(bad)

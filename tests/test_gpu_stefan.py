@@ -1,15 +1,20 @@
 """Heated wall and phase-dependent transport: oracle parity and the Stefan problem (Sec. III E).
 
 Set-up (the paper's, turned so that x runs away from the wall): a 100 x 5 channel, heated no-slip
-wall at x = -1/2 (halfway bounce-back, T = T_w), convective outlet at x = 99 (U = 0, no inflow),
-periodic in y; vapour diffusivity alpha_v = 0.1, liquid diffusivity 0.01 (the liquid carries little
-heat, as the analytical solution assumes), vapour Prandtl number 1.5; the wall ghosts carry rho_v.
+wall at x = -1/2 (halfway bounce-back, T = T_w), convective outlet at x = 99 moving with the local
+outflow velocity (outlet_kind 1: the liquid displaced by the growing vapour leaves), periodic in y;
+vapour diffusivity alpha_v = 0.1 (the paper's value), vapour Prandtl number 1.5.  The paper states
+no liquid property for this test; the analytical solution assumes liquid that stays at T_sat, so
+the liquid here carries little heat: alpha_l = 0.001.  (Measured with the oracle: the diffuse
+interface sits slightly above T_sat, and heat conducted into the liquid is lost to evaporation --
+beta comes out -11 %, -11 %, +0 % of the root with alpha_l = 0.01, -3.7 %, -3.9 %, +3.3 % with
+0.001, -2.6 %, -2.9 %, +3.7 % with 0.0003.)  The wall ghosts carry rho_v.
 Initial state: vapour up to 5.5 from the wall with the analytical temperature profile of that
 moment, saturated liquid beyond.  The analytical interface is y_i = 2 beta sqrt(alpha_v t) with
 beta exp(beta^2) erf(beta) = c_p dT / (h_fg sqrt(pi)) (latent heat from the library's Maxwell
 relation).  Pins: y_i^2 grows linearly in t while the vapour layer is resolved (from 3x to 6x the
-interface width; correlation > 0.995) with beta within 15 % of the root (measured: about 0.9 of it).
-Parity unpinned beyond that: the paper shows this only in a figure.
+interface width; correlation > 0.995) with beta within 5 % of the root in all three cases of
+the paper.
 """
 import json
 import math
@@ -20,7 +25,7 @@ import pytest
 
 import oracle
 from paper_1912_02018_amd import analysis
-from paper_1912_02018_amd.config import BC_WALL_OUTLET, FP64, LBMConfig
+from paper_1912_02018_amd.config import BC_WALL_OUTLET, FP64, OUTLET_LOCAL, LBMConfig
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +40,9 @@ def lbm_mod():
 
 def stefan_case(lbm, tr, dT):
     sat = lbm.saturation(LBMConfig(Tr_sat=tr))
-    cfg = LBMConfig(nx=100, ny=5, bc_x=BC_WALL_OUTLET, rk_stages=4, nu=0.15, nu_vapor=0.15, alpha_T=0.01,
+    cfg = LBMConfig(nx=100, ny=5, bc_x=BC_WALL_OUTLET, rk_stages=4, nu=0.15, nu_vapor=0.15, alpha_T=0.001,
                     alpha_vapor=0.1, Tr_sat=tr, dTr_wall=dT / sat["Tc"], rho_l=sat["rho_l"], rho_v=sat["rho_v"],
-                    rho_wall=sat["rho_v"], u_in=0.0, precision=FP64)
+                    rho_wall=sat["rho_v"], u_in=0.0, precision=FP64, outlet_kind=OUTLET_LOCAL)
     beta = analysis.stefan_beta(cfg.cv, dT, sat["h_fg"])
     return cfg, sat, beta
 
@@ -64,7 +69,7 @@ def interface(rho, sat):
 
 def test_wall_and_phase_properties_match_oracle(lbm_mod):
     cfg, sat, beta = stefan_case(lbm_mod, 0.86, 0.010)
-    cfg = cfg.replace(nu=0.05)   # different liquid and vapour viscosities too
+    cfg = cfg.replace(nu=0.05, alpha_T=0.01)   # different liquid and vapour viscosities too
     R, U, V, T, _ = initial_fields(cfg, sat, beta)
     g = lbm_mod.Simulation(cfg)
     o = oracle.Sim(cfg)
@@ -106,4 +111,4 @@ def test_stefan_interface_growth(lbm_mod, tr, dT):
     print(f"Stefan T_r {tr} dT {dT}: beta {beta:.5f} simulated {bsim:.5f} ({bsim / beta - 1:+.3f}), "
           f"corr {corr:.5f}, samples {len(ts)}, steps {sim.step_count}", flush=True)
     assert corr > 0.995
-    assert abs(bsim / beta - 1.0) < 0.15
+    assert abs(bsim / beta - 1.0) < 0.05
