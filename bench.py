@@ -360,9 +360,11 @@ def align(sim, period: int):
 
 def timed_windows(torch, sim, steps, repeats, period):
     """`repeats` windows of exactly `steps` steps, each starting at a multiple of the launch period and
-    bracketed by device synchronisations; returns the median window's milliseconds and wall-clock
-    seconds, and every window's milliseconds."""
+    bracketed by device synchronisations, after one untimed window; returns the median window's
+    milliseconds and wall-clock seconds, and every window's milliseconds."""
     reps, walls = [], []
+    align(sim, period)
+    sim.step(steps)      # untimed: captures the graph of the period if the library replays one
     for _ in range(max(1, repeats)):
         align(sim, period)
         ms, wall = timed_steps(torch, sim, steps)
