@@ -116,6 +116,18 @@ size_t lbm_workspace_bytes(const lbm_config *cfgs, int n_runs);
 int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes,
                void *hip_stream, lbm_handle **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): lbm_create without a caller workspace.  The handle's workspace
+ * is a static device array of LBM_STATIC_WORKSPACE_BYTES that the library holds on every device it
+ * runs on until the process ends; this call allocates no device memory.  Every static handle of a
+ * device shares that device's array: creating one waits for the device (hipDeviceSynchronize) and
+ * takes the array over, after which every earlier static handle of the device refuses further
+ * calls with LBM_ESTATE (lbm_destroy still releases it); static handles of one device must not be
+ * used concurrently.  Runs whose workspace (lbm_workspace_bytes) exceeds the array are refused with
+ * LBM_ENOMEM.  Otherwise as lbm_create (same arguments, states and results). */
+#define LBM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int lbm_create_static(const lbm_config *cfgs, int n_runs, void *hip_stream, lbm_handle **out);
+
 /* Advance every run by n_steps coupled steps (asynchronous unless check_every > 0, in which
  * case the call waits at its end and returns LBM_EUNSTABLE if a check failed). */
 int lbm_step(lbm_handle *h, int n_steps);

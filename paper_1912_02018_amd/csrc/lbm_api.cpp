@@ -59,6 +59,11 @@ struct lbm_handle {
     std::vector<Group> groups;
     hipEvent_t fork = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
+    // lbm_create_static: the workspace is the device's static array, valid until the next
+    // lbm_create_static on that device (generation `gen`)
+    bool static_ws = false;
+    int device = -1;
+    unsigned long long gen = 0;
     std::string err;
 };
 
@@ -455,9 +460,27 @@ int build_tiles(lbm_handle *h)
     return LBM_OK;
 }
 
-int check_run(lbm_handle *h, int run)
+// generation of each device's static workspace: bumped by every lbm_create_static on the device
+std::mutex g_static_mu;
+std::map<int, unsigned long long> g_static_gen;
+
+// a NULL handle is invalid; a static-workspace handle whose memory a later lbm_create_static on its
+// device took over may no longer launch anything
+int check_handle(lbm_handle *h)
 {
     if (!h) return LBM_EINVAL;
+    if (h->static_ws) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_gen[h->device] != h->gen)
+            return fail(h, LBM_ESTATE, "the static workspace of device %d now belongs to a later lbm_create_static",
+                        h->device);
+    }
+    return LBM_OK;
+}
+
+int check_run(lbm_handle *h, int run)
+{
+    if (int rc = check_handle(h)) return rc;
     if (run < 0 || run >= h->n_runs) return fail(h, LBM_EINVAL, "run index %d out of range", run);
     return LBM_OK;
 }
@@ -511,8 +534,40 @@ size_t lbm_workspace_bytes(const lbm_config *cfgs, int n_runs)
 static int set_fields_impl(lbm_handle *h, int run, const double *rho, const double *ux, const double *uy,
                            const double *T, int ux_seed_dir);
 
+static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                       lbm_handle **out, int static_device);
+
 int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                lbm_handle **out)
+{
+    return create_impl(cfgs, n_runs, dev_workspace, ws_bytes, hip_stream, out, -1);
+}
+
+int lbm_create_static(const lbm_config *cfgs, int n_runs, void *hip_stream, lbm_handle **out)
+{
+    const Range range("lbm_create_static");
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int prec, rk;
+    int rc = validate(cfgs, n_runs, &prec, &rk, nullptr);
+    if (rc != LBM_OK) return rc;
+    const size_t need = layout(cfgs, n_runs).total;
+    if (need > lbm::kStaticWorkspaceBytes)
+        return fail(nullptr, LBM_ENOMEM, "the runs need %zu bytes of workspace, more than the %zu of the static workspace",
+                    need, lbm::kStaticWorkspaceBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    void *ws = nullptr;
+    e = lbm::static_workspace(&ws);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "static workspace: %s", hipGetErrorString(e));
+    // the array is shared by every static handle of this device: earlier ones stop here
+    (void)hipDeviceSynchronize();
+    return create_impl(cfgs, n_runs, ws, lbm::kStaticWorkspaceBytes, hip_stream, out, dev);
+}
+
+static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                       lbm_handle **out, int static_device)
 {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -524,6 +579,12 @@ int lbm_create(const lbm_config *cfgs, int n_runs, void *dev_workspace, size_t w
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
 
     lbm_handle *h = new lbm_handle();
+    if (static_device >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        h->static_ws = true;
+        h->device = static_device;
+        h->gen = ++g_static_gen[static_device];
+    }
     h->n_runs = n_runs;
     h->precision = prec;
     h->rk = rk;
@@ -795,7 +856,7 @@ static long long pattern_length(const lbm_handle *h)
 int lbm_step(lbm_handle *h, int n_steps)
 {
     const Range range("lbm_step");
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (n_steps < 0) return fail(h, LBM_EINVAL, "negative step count");
     bool any_check = false;
     int max_warm = 0;
@@ -1017,7 +1078,7 @@ size_t lbm_checkpoint_bytes(const lbm_handle *h) { return h ? ckpt_bytes(h) : 0;
 int lbm_save(lbm_handle *h, void *host_buf, size_t bytes)
 {
     const Range range("lbm_save");
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
     if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint needs %zu bytes", ckpt_bytes(h));
     unsigned char *p = (unsigned char *)host_buf;
@@ -1044,7 +1105,7 @@ int lbm_save(lbm_handle *h, void *host_buf, size_t bytes)
 int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes)
 {
     const Range range("lbm_load");
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (!host_buf) return fail(h, LBM_EINVAL, "host_buf is NULL");
     if (bytes < ckpt_bytes(h)) return fail(h, LBM_EINVAL, "checkpoint of %zu bytes, this handle's take %zu", bytes, ckpt_bytes(h));
     const unsigned char *p = (const unsigned char *)host_buf;
@@ -1169,7 +1230,7 @@ int lbm_derived(lbm_handle *h, int run, double *out8)
 
 int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches)
 {
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (n_launches < 0) return fail(h, LBM_EINVAL, "negative launch count");
     if (kernel == LBM_KERNEL_STREAM_COLLIDE) {
         for (int k = 0; k < n_launches; ++k)
@@ -1205,7 +1266,7 @@ extern "C" {
 int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms)
 {
     const Range range("lbm_profile_steps");
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (!kernel_ms) return fail(h, LBM_EINVAL, "kernel_ms is NULL");
     if (n_steps < 1 || n_steps > LBM_MAX_PROFILE_STEPS)
         return fail(h, LBM_EINVAL, "profiled step count %d outside [1, %d]", n_steps, LBM_MAX_PROFILE_STEPS);
@@ -1261,7 +1322,7 @@ int lbm_variant_shape(int precision, int kernel, int variant, int *tx, int *ty, 
 
 int lbm_set_variant(lbm_handle *h, int kernel, int variant)
 {
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (kernel < 0 || kernel > 1 || variant < 0 || variant >= lbm::variant_count(h->precision, kernel))
         return fail(h, LBM_EINVAL, "no variant %d of kernel %d", variant, kernel);
     const int old = h->var[kernel];
@@ -1320,7 +1381,7 @@ static int time_pseudo_steps(lbm_handle *h, int n)
 int lbm_autotune(lbm_handle *h, int launches, int *best)
 {
     const Range range("lbm_autotune");
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     const std::string key = tune_key(h);
     if (launches < 0) {
         std::pair<int, int> hit(-1, -1);
@@ -1380,7 +1441,7 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
 
 int lbm_set_option(lbm_handle *h, int option, int value)
 {
-    if (!h) return LBM_EINVAL;
+    if (int rc_ = check_handle(h)) return rc_;
     if (option == LBM_OPT_GRAPHS) {
         h->use_graphs = value != 0;
         drop_graphs(h);

@@ -17,6 +17,8 @@ constexpr int kTangents = 4;
 constexpr int kAcc = 16;
 // probe limit of the tangent precision (its per-probe heat flux carries the tangents in LDS)
 constexpr int kMaxTangentProbes = 1024;
+// size of the per-device static workspace of handles created by lbm_create_static
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
 
 // Per-run description read by every kernel.  Physical constants are kept in FP64 and converted
 // to the compute type inside the kernels.
@@ -72,6 +74,10 @@ Variant variant_shape(int precision, int kernel, int v);
 struct Timing {
     hipEvent_t start, stop;
 };
+
+// Device address of the current device's static workspace (kStaticWorkspaceBytes, 256-byte
+// aligned), looked up once per device.
+hipError_t static_workspace(void **ptr);
 
 // Launchers (each enqueues on `stream`; returns a hipError_t).
 hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream);

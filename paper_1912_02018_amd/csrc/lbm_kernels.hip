@@ -25,6 +25,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 namespace lbm {
@@ -1672,6 +1674,31 @@ hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int pt, i
         k_diag_final<float><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
     }
     return hipGetLastError();
+}
+
+// Device memory of the handles created without a caller workspace (lbm_create_static), for callers
+// that cannot allocate: one copy of this array per device, held for the life of the process.  In host
+// code its name is only a stand-in; kernels receive the device address found by static_workspace().
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+hipError_t static_workspace(void **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;   // per device
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidSymbol;
+        it = addr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
 }
 
 hipError_t launch_init(int precision, const RunDev *runs_dev, int run, long long nodes, hipStream_t stream)

@@ -39,7 +39,9 @@ EXPORTED = [
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
     "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation", "lbm_profile_steps",
     "lbm_get_option", "lbm_stream_group_runs", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
+    "lbm_create_static",
 ]
+STATIC_WORKSPACE_BYTES = 64 << 20
 OPT_GRAPHS, OPT_STREAM_GROUPS = 0, 1
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
 
@@ -72,6 +74,7 @@ def load_library():
     L.lbm_workspace_bytes.argtypes = [cfgp, i32]
     L.lbm_workspace_bytes.restype = C.c_size_t
     L.lbm_create.argtypes = [cfgp, i32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_create_static.argtypes = [cfgp, i32, vp, C.POINTER(vp)]
     L.lbm_step.argtypes = [vp, i32]
     L.lbm_fields.argtypes = [vp, i32, dp, dp, dp, dp, C.POINTER(C.c_uint8)]
     L.lbm_set_fields.argtypes = [vp, i32, dp, dp, dp, dp]
@@ -144,7 +147,10 @@ def saturation(cfg: LBMConfig) -> dict:
 class Simulation:
     """One handle stepping one or more runs on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, cfgs, device: str = "cuda", stream=None):
+    def __init__(self, cfgs, device: str = "cuda", stream=None, static_workspace: bool = False):
+        """static_workspace: create the handle on the library's static device array
+        (lbm_create_static; no device allocation, the previous static handle of the device stops
+        working) instead of a torch workspace."""
         import torch
         if isinstance(cfgs, LBMConfig):
             cfgs = [cfgs]
@@ -153,14 +159,19 @@ class Simulation:
         self._L = L
         n = len(self.cfgs)
         arr = (lbm_config * n)(*[to_c_config(c) for c in self.cfgs])
-        nbytes = L.lbm_workspace_bytes(arr, n)
-        if nbytes == 0:
-            raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        dev = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         h = C.c_void_p()
-        rc = L.lbm_create(arr, n, C.c_void_p(self.workspace.data_ptr()), nbytes,
-                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if static_workspace:
+            self.workspace = None
+            rc = L.lbm_create_static(arr, n, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            nbytes = L.lbm_workspace_bytes(arr, n)
+            if nbytes == 0:
+                raise LBMError(LBM_EINVAL, L.lbm_last_error(None).decode())
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            rc = L.lbm_create(arr, n, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != LBM_OK:
             raise LBMError(rc, L.lbm_last_error(None).decode())
         self.h = h
