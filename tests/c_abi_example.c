@@ -31,7 +31,7 @@ static const struct {
     FIELD_D(dTr_wall), FIELD_D(G), FIELD_D(sigma), FIELD_D(gx), FIELD_D(gy), FIELD_D(rho_gref),
     FIELD_D(rho_l), FIELD_D(rho_v), FIELD_D(rho_wall), FIELD_D(u_in), FIELD_D(alpha_T), FIELD_D(cv),
     FIELD_I(precision), FIELD_I(check_every), FIELD_D(rho_ref_shift), FIELD_D(nu_vapor),
-    FIELD_D(alpha_vapor), FIELD_I(outlet_kind),
+    FIELD_D(alpha_vapor), FIELD_I(outlet_kind), FIELD_I(pad_),
 };
 
 static int fail_lib(const lbm_handle *h, const char *what, int rc)
