@@ -236,10 +236,12 @@ def reduced_storage_report(lbm, steps=1000):
     return {"workload": "boiling-cylinder-1024x512-R32-Re30000-rk4", "steps_after_warmup": steps, **out}
 
 
-def sensitivity_run(lbm, steps=4000, average_from=2000):
+def sensitivity_run(lbm, steps=4000, average_from=2000, checkpoint_every=200):
     """Time-averaged Nu of the 512x256 channel (R 16, Re 300, superheat 0.1 T_c, no warm-up) over
-    steps 2000..3999 and its gradient with respect to (superheat, u_in, acentric factor, tau), from
-    one run of the forward-mode tangent precision (FP64 values + 4 derivatives per value)."""
+    steps 2000..3999 and its gradient with respect to (superheat, u_in, acentric factor, tau), by the
+    reverse sweep (hand-written adjoint, checkpoints every 200 steps and recompute) and by one run of
+    the forward-mode tangent precision (FP64 values + 4 derivatives per value)."""
+    import numpy as np
     import torch
     from paper_1912_02018_amd import sensitivity
     from paper_1912_02018_amd.config import config5
@@ -249,10 +251,24 @@ def sensitivity_run(lbm, steps=4000, average_from=2000):
     J, g = sensitivity.nu_average_and_gradient(cfg, steps, average_from)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"workload": "boiling-cylinder-512x256-R16-Re300-rk4-f64-tangent4", "steps": steps,
-            "average_from": average_from, "J_mean_nu": J,
-            "dJ_dtheta": dict(zip(sensitivity.TANGENT_PARAMS, [float(x) for x in g])),
-            "wall_s": round(dt, 3), "mlups_incl_setup": round(cfg.nx * cfg.ny * steps / dt / 1e6, 1)}
+    sim = lbm.Simulation(cfg.replace(diag_every=1))
+    ws_bytes = sim._L.lbm_nu_gradient_bytes(sim.h, steps, checkpoint_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ja, ga = sim.nu_gradient(steps, average_from, checkpoint_every)
+    torch.cuda.synchronize()
+    dta = time.perf_counter() - t0
+    sim.close()
+    rel = float(np.abs(np.asarray(ga) - np.asarray(g)).max() / np.abs(np.asarray(g)).max())
+    return {"workload": "boiling-cylinder-512x256-R16-Re300-rk4-f64", "steps": steps,
+            "average_from": average_from, "J_mean_nu": Ja,
+            "dJ_dtheta": dict(zip(sensitivity.TANGENT_PARAMS, [float(x) for x in ga])),
+            "adjoint": {"method": f"reverse sweep, checkpoints every {checkpoint_every} steps, segments recomputed",
+                        "wall_s": round(dta, 3), "device_workspace_bytes": int(ws_bytes)},
+            "tangent": {"method": "forward mode, FP64 + 4 derivatives per value", "J_mean_nu": J,
+                        "dJ_dtheta": dict(zip(sensitivity.TANGENT_PARAMS, [float(x) for x in g])),
+                        "wall_s": round(dt, 3), "mlups_incl_setup": round(cfg.nx * cfg.ny * steps / dt / 1e6, 1)},
+            "adjoint_vs_tangent_max_rel": rel}
 
 
 def hbm_resident_run(lbm, steps=200):

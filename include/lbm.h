@@ -185,6 +185,45 @@ int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, doubl
  * Either pointer may be NULL (4 doubles each).  Waits for the stream. */
 int lbm_nu_tangent(lbm_handle *h, int run, double *dnu, double *dnu_time_avg);
 
+/* Reverse-mode adjoint (discrete adjoint of the step, hand-written), for objectives built from the
+ * wall Nusselt number of Sec. IV B, with respect to the same four parameters as lbm_nu_tangent
+ * (dTr_wall, u_in, acentric, tau; rho_l, rho_v, T_sat, c_v and the geometry held).  Covers FP64 runs
+ * (precision LBM_FP64) with bc_x LBM_BC_PERIODIC or LBM_BC_INLET_OUTLET, constant transport
+ * properties (nu_vapor, alpha_vapor <= 0), outlet_kind LBM_OUTLET_U_IN and nx, ny >= 5; other runs
+ * are refused with LBM_EINVAL.
+ *
+ * lbm_adjoint_step: the adjoint of one step of run `run` from its current state n (the handle is
+ * not advanced).  adj_in holds the adjoint of state n+1, adj_out receives that of state n; both are
+ * device buffers of lbm_adjoint_state_bytes bytes in FP64, laid out with P = ny * pitch and
+ * pitch = nx rounded up to a multiple of 64: lambda_f*[i] at element i*P + y*pitch + x (i = 0..8),
+ * lambda_T at 9P + y*pitch + x, lambda_hist[m] (populations 2, 6, 8 of the last column) at
+ * 10P + m*ny + y, and the gradient accumulated so far, dJ/dtheta[4], at 10P + 3ny; adj_out's
+ * gradient is adj_in's plus this step's contribution.  nu_weight is dJ/dNu_n, the weight of this
+ * step's Nu sample (the Nu of state n that lbm_step accumulates) in the objective (0: none).
+ * scratch: device memory of lbm_adjoint_scratch_bytes bytes (intermediates of the recomputed
+ * step).  dJ_dparams (host, 4 doubles, may be NULL) receives adj_out's gradient (the call then
+ * waits for the stream).  The adjoint is exact for the discrete FP64 step up to rounding: it agrees
+ * with the tangent precision's derivatives.  The *_bytes calls return 0 for unsupported runs. */
+size_t lbm_adjoint_state_bytes(lbm_handle *h, int run);
+size_t lbm_adjoint_scratch_bytes(lbm_handle *h, int run);
+int lbm_adjoint_step(lbm_handle *h, int run, double nu_weight, const void *adj_in, void *adj_out, void *scratch,
+                     size_t scratch_bytes, double *dJ_dparams);
+
+/* J = mean Nu of the states average_from .. steps-1 of the next `steps` steps of a one-run handle,
+ * and dJ/dtheta[4] by the reverse sweep: the forward run stores a checkpoint of the state every
+ * checkpoint_every steps in dev_ws; then, segment by segment from the last, the segment is
+ * recomputed from its checkpoint keeping every state, and lbm_adjoint_step runs over it backwards.
+ * The gradient is that of J through the steps taken here, from the current state taken as given;
+ * a run still in lbm_create's default state also gets that state's dependence on u_in, and solid
+ * nodes' T_w always counts.  The handle ends in the state after `steps` steps with the Nu time
+ * average of the window (as lbm_step would leave it with diag_every = 1 and the average restarted
+ * at average_from).  dev_ws: caller-owned device memory, 256-byte aligned, of
+ * lbm_nu_gradient_bytes(h, steps, checkpoint_every) bytes (about (steps / checkpoint_every +
+ * checkpoint_every) FP64 states).  J and dJ_dparams (host) may be NULL.  Waits for the stream. */
+size_t lbm_nu_gradient_bytes(lbm_handle *h, int steps, int checkpoint_every);
+int lbm_nu_gradient(lbm_handle *h, int steps, int average_from, int checkpoint_every, void *dev_ws, size_t ws_bytes,
+                    double *J, double *dJ_dparams);
+
 /* Restart the time average of Nu (and of its tangents) of one run: the next lbm_step
  * accumulations start a new window.  Waits for the stream. */
 int lbm_reset_time_average(lbm_handle *h, int run);

@@ -49,6 +49,8 @@ struct lbm_handle {
     long long step = 0;
     bool use_graphs = true;
     std::vector<StepGraph> graphs;
+    // per run: still in the default state of lbm_create (its initial fields depend on u_in)
+    std::vector<char> default_state;
     // stream groups (LBM_OPT_STREAM_GROUPS > 1): contiguous ranges of runs stepped on streams of their
     // own, so that one group's temperature update overlaps another group's streaming
     struct Group {
@@ -638,9 +640,11 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
         R.dphi_A = -R.kappa * (1.0 + R.kappa) / std::sqrt(R.Tc);
         R.dphi_B = R.kappa * R.kappa / R.Tc;
         R.inv_cv = 1.0 / R.cv;
-        if (prec == 4) {
-            // tangent directions: 0 superheat dTr_wall, 1 u_in, 2 acentric factor, 3 tau (at fixed
-            // nu/alpha ratio); the coexistence densities, T_sat and the other constants are held
+        {
+            // derivatives of the parameter-dependent constants (read by the tangent precision and by
+            // the adjoint of FP64 runs) along the directions: 0 superheat dTr_wall, 1 u_in, 2 acentric
+            // factor, 3 tau (at fixed nu/alpha ratio); the coexistence densities, T_sat and the other
+            // constants are held
             const double tau = k.nu / (1.0 / 3.0) + 0.5;
             const double dkappa = 1.54226 - 2.0 * 0.26992 * k.acentric;
             R.t_T_w[0] = pr.Tc;
@@ -716,6 +720,7 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
             return rc;
         }
     }
+    h->default_state.assign(n_runs, 1);
     *out = h;
     return LBM_OK;
 }
@@ -752,6 +757,7 @@ static int set_fields_impl(lbm_handle *h, int run, const double *rho, const doub
     HIPCHK(h, lbm::launch_init(h->precision, h->runs_dev, run, (long long)R.nx * R.ny, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->step = 0;
+    if (run < (int)h->default_state.size()) h->default_state[run] = 0;
     return LBM_OK;
 }
 
@@ -784,6 +790,7 @@ static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *th
     }
     if (thermal_ran) *thermal_ran = thermal;
     if (diag_ran) *diag_ran = diag;
+    std::fill(h->default_state.begin(), h->default_state.end(), 0);
     h->pf ^= 1;
     h->ph ^= 1;
     h->step += 1;
@@ -815,6 +822,7 @@ static int enqueue_step_groups(lbm_handle *h)
         }
     }
     if (thermal) h->pt ^= 1;
+    std::fill(h->default_state.begin(), h->default_state.end(), 0);
     h->pf ^= 1;
     h->ph ^= 1;
     h->step += 1;
@@ -916,6 +924,7 @@ int lbm_step(lbm_handle *h, int n_steps)
             for (long long k = 0; k < reps; ++k) HIPCHK(h, hipGraphLaunch(g->exec, h->stream));
             // parities return to their values after an even-length window
             h->pt = pt0;
+            std::fill(h->default_state.begin(), h->default_state.end(), 0);
             h->step += reps * L;
             remaining -= reps * L;
             continue;
@@ -1029,6 +1038,7 @@ int lbm_set_state(lbm_handle *h, int run, const double *fstar, const double *his
     if ((rc = upload_plane(h, R, R.T[h->pt], Tw.data(), 0))) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->step = step;
+    h->default_state[run] = 0;
     return LBM_OK;
 }
 
@@ -1129,6 +1139,7 @@ int lbm_load(lbm_handle *h, const void *host_buf, size_t bytes)
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->step = hd.step;
+    std::fill(h->default_state.begin(), h->default_state.end(), 0);
     drop_graphs(h);
     return LBM_OK;
 }
@@ -1502,6 +1513,175 @@ int lbm_stream_group_runs(const lbm_handle *h, int group, int *run0, int *run1)
     if (run0) *run0 = h->groups.empty() ? 0 : h->groups[group].run0;
     if (run1) *run1 = h->groups.empty() ? h->n_runs : h->groups[group].run1;
     return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// the adjoint covers FP64 runs with x periodic or a velocity inlet / convective outlet at speed u_in,
+// constant transport properties and grids of at least 5 x 5
+int adjoint_supported(lbm_handle *h, int run)
+{
+    const lbm_config &k = h->cfgs[run];
+    if (h->precision != LBM_FP64) return fail(h, LBM_EINVAL, "the adjoint needs an FP64 handle");
+    if (k.bc_x != LBM_BC_PERIODIC && k.bc_x != LBM_BC_INLET_OUTLET)
+        return fail(h, LBM_EINVAL, "the adjoint covers periodic and inlet/outlet channels only");
+    if (h->runs[run].phase_props || k.outlet_kind != LBM_OUTLET_U_IN)
+        return fail(h, LBM_EINVAL, "the adjoint covers constant transport properties and the outlet speed u_in only");
+    if (k.nx < 5 || k.ny < 5) return fail(h, LBM_EINVAL, "the adjoint needs nx, ny >= 5");
+    return LBM_OK;
+}
+
+size_t adj_state_bytes(const RunDev &R) { return sizeof(double) * lbm::adjoint_state_doubles(R.nx, R.ny, R.pitch); }
+size_t adj_scratch_bytes(const RunDev &R) { return sizeof(double) * lbm::adjoint_scratch_doubles(R.nx, R.ny, R.pitch); }
+// raw FP64 state of a run in a device slot: f* [9] planes, T plane, outlet history [3][ny]
+size_t state_doubles(const RunDev &R) { return 10 * (size_t)R.ny * R.pitch + 3 * (size_t)R.ny; }
+
+int copy_state(lbm_handle *h, int run, double *slot, bool out)
+{
+    const RunDev &R = h->runs[run];
+    const size_t P = (size_t)R.ny * R.pitch;
+    struct { void *dev; double *sl; size_t n; } parts[3] = {
+        {R.f[h->pf], slot, 9 * P}, {R.T[h->pt], slot + 9 * P, P}, {R.hist[h->ph], slot + 10 * P, 3 * (size_t)R.ny}};
+    for (auto &p : parts) {
+        if (out) HIPCHK(h, hipMemcpyAsync(p.sl, p.dev, sizeof(double) * p.n, hipMemcpyDeviceToDevice, h->stream));
+        else HIPCHK(h, hipMemcpyAsync(p.dev, p.sl, sizeof(double) * p.n, hipMemcpyDeviceToDevice, h->stream));
+    }
+    return LBM_OK;
+}
+
+size_t gradient_bytes(const RunDev &R, int steps, int every)
+{
+    const size_t nck = (size_t)((steps + every - 1) / every);
+    const size_t sd = align256(sizeof(double) * state_doubles(R));
+    return (nck + (size_t)every + 1) * sd + 2 * align256(adj_state_bytes(R)) + align256(adj_scratch_bytes(R));
+}
+}  // namespace
+
+extern "C" {
+
+size_t lbm_adjoint_state_bytes(lbm_handle *h, int run)
+{
+    if (check_run(h, run) || adjoint_supported(h, run)) return 0;
+    return adj_state_bytes(h->runs[run]);
+}
+
+size_t lbm_adjoint_scratch_bytes(lbm_handle *h, int run)
+{
+    if (check_run(h, run) || adjoint_supported(h, run)) return 0;
+    return adj_scratch_bytes(h->runs[run]);
+}
+
+int lbm_adjoint_step(lbm_handle *h, int run, double nu_weight, const void *adj_in, void *adj_out, void *scratch,
+                     size_t scratch_bytes, double *dJ_dparams)
+{
+    const Range range("lbm_adjoint_step");
+    int rc = check_run(h, run);
+    if (rc || (rc = adjoint_supported(h, run))) return rc;
+    const RunDev &R = h->runs[run];
+    if (!adj_in || !adj_out || adj_in == adj_out) return fail(h, LBM_EINVAL, "adj_in and adj_out must be distinct device buffers");
+    if (!scratch || scratch_bytes < adj_scratch_bytes(R))
+        return fail(h, LBM_ENOMEM, "the adjoint step needs %zu bytes of scratch", adj_scratch_bytes(R));
+    HIPCHK(h, lbm::launch_adjoint_step(h->runs_dev, run, R, (const double *)R.f[h->pf], (const double *)R.hist[h->ph],
+                                       (const double *)R.T[h->pt], (const double *)adj_in, (double *)adj_out,
+                                       (double *)scratch, h->step, nu_weight, h->stream));
+    if (dJ_dparams) {
+        HIPCHK(h, hipMemcpyAsync(dJ_dparams, (const double *)adj_out + (adj_state_bytes(R) / sizeof(double) - lbm::kTangents),
+                                 sizeof(double) * lbm::kTangents, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return LBM_OK;
+}
+
+size_t lbm_nu_gradient_bytes(lbm_handle *h, int steps, int checkpoint_every)
+{
+    if (check_handle(h) || h->n_runs != 1 || adjoint_supported(h, 0) || steps < 1 || checkpoint_every < 1) return 0;
+    return gradient_bytes(h->runs[0], steps, checkpoint_every);
+}
+
+int lbm_nu_gradient(lbm_handle *h, int steps, int average_from, int checkpoint_every, void *dev_ws, size_t ws_bytes,
+                    double *J, double *dJ_dparams)
+{
+    const Range range("lbm_nu_gradient");
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (h->n_runs != 1) return fail(h, LBM_EINVAL, "the Nu gradient takes a handle of one run");
+    if ((rc = adjoint_supported(h, 0))) return rc;
+    if (steps < 1 || average_from < 0 || average_from >= steps || checkpoint_every < 1)
+        return fail(h, LBM_EINVAL, "need steps >= 1, 0 <= average_from < steps, checkpoint_every >= 1");
+    if (h->runs[0].np == 0) return fail(h, LBM_EINVAL, "the run has no cylinder (no wall Nusselt number)");
+    const RunDev &R = h->runs[0];
+    const int K = checkpoint_every;
+    if (!dev_ws || ws_bytes < gradient_bytes(R, steps, K))
+        return fail(h, LBM_ENOMEM, "the Nu gradient needs %zu bytes of device workspace", gradient_bytes(R, steps, K));
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(h, LBM_EINVAL, "the workspace must be 256-byte aligned");
+    const int nck = (steps + K - 1) / K;
+    const size_t sd = align256(sizeof(double) * state_doubles(R)) / sizeof(double);
+    const size_t ad = align256(adj_state_bytes(R)) / sizeof(double);
+    double *ckpt = (double *)dev_ws, *store = ckpt + (size_t)nck * sd, *fin = store + (size_t)K * sd;
+    double *adj[2] = {fin + sd, fin + sd + ad};
+    double *scr = adj[1] + ad;
+    const bool deflt = h->default_state[0] != 0;
+    const long long n0 = h->step;
+    const int diag0 = h->cfgs[0].diag_every;
+    auto finish = [&](int code) {
+        h->cfgs[0].diag_every = diag0;
+        drop_graphs(h);
+        return code;
+    };
+    // forward: checkpoints every K steps, Nu sampled every step of the averaging window
+    h->cfgs[0].diag_every = 1;
+    drop_graphs(h);
+    for (int c = 0; c < nck; ++c) {
+        const int s0 = c * K, s1 = std::min(steps, s0 + K);
+        if ((rc = copy_state(h, 0, ckpt + (size_t)c * sd, true))) return finish(rc);
+        if (average_from >= s0 && average_from < s1) {
+            if ((rc = lbm_step(h, average_from - s0)) || (rc = lbm_reset_time_average(h, 0)) ||
+                (rc = lbm_step(h, s1 - average_from)))
+                return finish(rc);
+        } else if ((rc = lbm_step(h, s1 - s0))) {
+            return finish(rc);
+        }
+    }
+    double acc[lbm::kAcc];
+    HIPCHK(h, hipMemcpyAsync(acc, R.acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const double samples = acc[4];
+    if (J) *J = samples > 0 ? acc[3] / samples : 0.0;
+    if ((rc = copy_state(h, 0, fin, true))) return finish(rc);
+    // reverse sweep over the segments, each recomputed from its checkpoint
+    h->cfgs[0].diag_every = 0;
+    drop_graphs(h);
+    HIPCHK(h, hipMemsetAsync(adj[0], 0, sizeof(double) * ad, h->stream));
+    int cur = 0;
+    for (int c = nck - 1; c >= 0; --c) {
+        const int s0 = c * K, s1 = std::min(steps, s0 + K);
+        if ((rc = copy_state(h, 0, ckpt + (size_t)c * sd, false))) return finish(rc);
+        h->step = n0 + s0;
+        for (int s = s0; s < s1; ++s) {
+            if ((rc = copy_state(h, 0, store + (size_t)(s - s0) * sd, true))) return finish(rc);
+            if ((rc = enqueue_step(h))) return finish(rc);
+        }
+        for (int s = s1 - 1; s >= s0; --s) {
+            const long long n = n0 + s;
+            const double w = (s >= average_from && n >= h->cfgs[0].warmup_steps && samples > 0) ? 1.0 / samples : 0.0;
+            const double *st = store + (size_t)(s - s0) * sd;
+            const size_t P = (size_t)R.ny * R.pitch;
+            HIPCHK(h, lbm::launch_adjoint_step(h->runs_dev, 0, R, st, st + 10 * P, st + 9 * P, adj[cur], adj[cur ^ 1], scr, n, w,
+                                               h->stream));
+            cur ^= 1;
+        }
+    }
+    HIPCHK(h, lbm::launch_adjoint_initial(h->runs_dev, 0, adj[cur], deflt, h->stream));
+    double g[lbm::kTangents];
+    HIPCHK(h, hipMemcpyAsync(g, adj[cur] + (adj_state_bytes(R) / sizeof(double) - lbm::kTangents), sizeof(g),
+                             hipMemcpyDeviceToHost, h->stream));
+    // the handle ends in the forward run's final state
+    if ((rc = copy_state(h, 0, fin, false))) return finish(rc);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->step = n0 + steps;
+    if (dJ_dparams) std::memcpy(dJ_dparams, g, sizeof(g));
+    return finish(LBM_OK);
 }
 
 int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }

@@ -92,4 +92,15 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
 hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int parity_t, int accumulate,
                        hipStream_t stream);
 
+// Reverse-mode adjoint of one FP64 step of run `run` (lbm_adjoint.hip).  Rh: host copy of the run's
+// descriptor.  fs, hist, T: state n; ain / aout: adjoint states of n+1 / n (adjoint_state_doubles);
+// scratch: adjoint_scratch_doubles doubles.
+size_t adjoint_scratch_doubles(int nx, int ny, int pitch);
+size_t adjoint_state_doubles(int nx, int ny, int pitch);
+hipError_t launch_adjoint_step(const RunDev *runs_dev, int run, const RunDev &Rh, const double *fs, const double *hist,
+                               const double *T, const double *ain, double *aout, double *scratch, long long step,
+                               double nu_weight, hipStream_t stream);
+// adds the initial state's parameter dependence to the accumulated gradient of the adjoint state adj
+hipError_t launch_adjoint_initial(const RunDev *runs_dev, int run, double *adj, bool default_state, hipStream_t stream);
+
 }  // namespace lbm

@@ -39,7 +39,8 @@ EXPORTED = [
     "lbm_variant_count", "lbm_variant_shape", "lbm_set_variant", "lbm_get_variant", "lbm_autotune",
     "lbm_set_option", "lbm_nu_tangent", "lbm_reset_time_average", "lbm_saturation", "lbm_profile_steps",
     "lbm_get_option", "lbm_stream_group_runs", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
-    "lbm_create_static",
+    "lbm_create_static", "lbm_adjoint_state_bytes", "lbm_adjoint_scratch_bytes", "lbm_adjoint_step",
+    "lbm_nu_gradient_bytes", "lbm_nu_gradient",
 ]
 STATIC_WORKSPACE_BYTES = 64 << 20
 OPT_GRAPHS, OPT_STREAM_GROUPS = 0, 1
@@ -75,6 +76,14 @@ def load_library():
     L.lbm_workspace_bytes.restype = C.c_size_t
     L.lbm_create.argtypes = [cfgp, i32, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.lbm_create_static.argtypes = [cfgp, i32, vp, C.POINTER(vp)]
+    L.lbm_adjoint_state_bytes.argtypes = [vp, i32]
+    L.lbm_adjoint_state_bytes.restype = C.c_size_t
+    L.lbm_adjoint_scratch_bytes.argtypes = [vp, i32]
+    L.lbm_adjoint_scratch_bytes.restype = C.c_size_t
+    L.lbm_adjoint_step.argtypes = [vp, i32, C.c_double, vp, vp, vp, C.c_size_t, dp]
+    L.lbm_nu_gradient_bytes.argtypes = [vp, i32, i32]
+    L.lbm_nu_gradient_bytes.restype = C.c_size_t
+    L.lbm_nu_gradient.argtypes = [vp, i32, i32, i32, vp, C.c_size_t, dp, dp]
     L.lbm_step.argtypes = [vp, i32]
     L.lbm_fields.argtypes = [vp, i32, dp, dp, dp, dp, C.POINTER(C.c_uint8)]
     L.lbm_set_fields.argtypes = [vp, i32, dp, dp, dp, dp]
@@ -315,6 +324,40 @@ class Simulation:
         d, da = np.zeros(4), np.zeros(4)
         self._check(self._L.lbm_nu_tangent(self.h, run, _dp(d), _dp(da)))
         return d, da
+
+    def adjoint_buffers(self, run: int = 0):
+        """(two adjoint-state buffers, scratch) as torch uint8 device tensors for adjoint_step."""
+        import torch
+        nb = self._L.lbm_adjoint_state_bytes(self.h, run)
+        ns = self._L.lbm_adjoint_scratch_bytes(self.h, run)
+        if nb == 0 or ns == 0:
+            raise LBMError(LBM_EINVAL, self._L.lbm_last_error(self.h).decode())
+        dev = torch.device("cuda", torch.cuda.current_device())
+        return (torch.zeros(nb, dtype=torch.uint8, device=dev), torch.zeros(nb, dtype=torch.uint8, device=dev),
+                torch.empty(ns, dtype=torch.uint8, device=dev))
+
+    def adjoint_step(self, adj_in, adj_out, scratch, nu_weight: float = 0.0, run: int = 0):
+        """Adjoint of one step from the current state (lbm_adjoint_step); returns the gradient
+        accumulated in adj_out, dJ/dtheta (4)."""
+        g = np.zeros(4)
+        self._check(self._L.lbm_adjoint_step(self.h, run, float(nu_weight), C.c_void_p(adj_in.data_ptr()),
+                                             C.c_void_p(adj_out.data_ptr()), C.c_void_p(scratch.data_ptr()),
+                                             scratch.numel(), _dp(g)))
+        return g
+
+    def nu_gradient(self, steps: int, average_from: int, checkpoint_every: int = 200):
+        """(J, dJ/dtheta) by the reverse sweep with checkpoints every checkpoint_every steps
+        (lbm_nu_gradient); advances the handle by `steps` steps."""
+        import torch
+        nb = self._L.lbm_nu_gradient_bytes(self.h, int(steps), int(checkpoint_every))
+        if nb == 0:
+            raise LBMError(LBM_EINVAL, self._L.lbm_last_error(self.h).decode())
+        ws = torch.empty(nb, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+        J, g = C.c_double(), np.zeros(4)
+        self._check(self._L.lbm_nu_gradient(self.h, int(steps), int(average_from), int(checkpoint_every),
+                                            C.c_void_p(ws.data_ptr()), nb, C.byref(J), _dp(g)))
+        del ws
+        return J.value, g
 
     def reset_time_average(self, run: int = 0):
         self._check(self._L.lbm_reset_time_average(self.h, run))

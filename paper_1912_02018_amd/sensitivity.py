@@ -1,10 +1,15 @@
 """Sensitivities of the time-averaged wall Nusselt number of a boiling run.
 
 J(theta) is the mean of Nu over the states average_from .. steps-1 of a run (Nu as defined for the
-heated cylinder, Sec. IV B), theta = (dTr_wall, u_in, acentric, tau).  The tangent precision of
-liblbm (LBM_F64_TANGENT) carries the derivatives of every value of the FP64 step along the four
-parameter directions (forward-mode dual numbers through the same kernels), so one run gives J and
-its exact discrete gradient.  ``NuTimeAverage`` exposes that as a torch.autograd.Function.
+heated cylinder, Sec. IV B), theta = (dTr_wall, u_in, acentric, tau).  Two exact routes to the
+discrete gradient of the FP64 step:
+  * reverse mode (``nu_average_and_gradient_adjoint``): liblbm's hand-written adjoint of the step run
+    backwards over the trajectory, which is recomputed segment by segment from checkpoints taken
+    every K steps (lbm_nu_gradient); its cost does not grow with the number of parameters;
+  * forward mode (``nu_average_and_gradient``): the tangent precision LBM_F64_TANGENT carries the
+    four derivatives of every value through the same kernels in one run.
+``NuTimeAverage`` is the torch.autograd.Function: forward runs the FP64 step for J, backward the
+reverse sweep (or, with mode="tangent", the tangent run).
 
 The coexistence densities rho_l, rho_v (the initial liquid, the gravity and wall densities and the
 Nu normalisation use them) are held fixed: ``hold_coexistence`` writes the values the library
@@ -16,10 +21,10 @@ import numpy as np
 import torch
 
 from . import lbm
-from .config import F64_TANGENT, TANGENT_PARAMS, LBMConfig
+from .config import F64_TANGENT, FP64, TANGENT_PARAMS, LBMConfig
 
-__all__ = ["TANGENT_PARAMS", "params_of", "with_params", "hold_coexistence",
-           "nu_average_and_gradient", "NuTimeAverage"]
+__all__ = ["TANGENT_PARAMS", "params_of", "with_params", "hold_coexistence", "nu_average",
+           "nu_average_and_gradient", "nu_average_and_gradient_adjoint", "NuTimeAverage"]
 
 
 def params_of(cfg: LBMConfig) -> np.ndarray:
@@ -61,18 +66,55 @@ def nu_average_and_gradient(cfg: LBMConfig, steps: int, average_from: int = 0):
     return J, dJ
 
 
+def nu_average(cfg: LBMConfig, steps: int, average_from: int = 0) -> float:
+    """J of the FP64 (or the configuration's) step: the mean Nu of the states average_from .. steps-1."""
+    if not 0 <= average_from < steps:
+        raise ValueError("need 0 <= average_from < steps")
+    sim = lbm.Simulation(cfg.replace(diag_every=1))
+    try:
+        sim.step(average_from)
+        sim.reset_time_average()
+        sim.step(steps - average_from)
+        return sim.wall_heat_flux()[2]
+    finally:
+        sim.close()
+
+
+def nu_average_and_gradient_adjoint(cfg: LBMConfig, steps: int, average_from: int = 0,
+                                    checkpoint_every: int = 200):
+    """(J, dJ/dtheta) of one FP64 run from its default state by the reverse sweep with
+    checkpoint-and-recompute every checkpoint_every steps."""
+    if not 0 <= average_from < steps:
+        raise ValueError("need 0 <= average_from < steps")
+    sim = lbm.Simulation(cfg.replace(precision=FP64, diag_every=1))
+    try:
+        return sim.nu_gradient(steps, average_from, checkpoint_every)
+    finally:
+        sim.close()
+
+
 class NuTimeAverage(torch.autograd.Function):
-    """J = NuTimeAverage.apply(theta, base_cfg, steps, average_from) for a float64 tensor theta of
-    the four parameters; backward returns grad_J * dJ/dtheta from the tangent run."""
+    """J = NuTimeAverage.apply(theta, base_cfg, steps, average_from, checkpoint_every, mode) for a
+    float64 tensor theta of the four parameters.  Forward: the FP64 run for J.  Backward:
+    grad_J * dJ/dtheta from the reverse sweep with checkpoints every checkpoint_every steps
+    (mode "adjoint", the default), or from the tangent run (mode "tangent")."""
 
     @staticmethod
-    def forward(ctx, theta, base: LBMConfig, steps: int, average_from: int):
-        cfg = with_params(base, theta.detach().cpu().numpy())
-        J, g = nu_average_and_gradient(cfg, steps, average_from)
-        ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
-        return theta.new_tensor(J)
+    def forward(ctx, theta, base: LBMConfig, steps: int, average_from: int, checkpoint_every: int = 200,
+                mode: str = "adjoint"):
+        if mode not in ("adjoint", "tangent"):
+            raise ValueError("mode is 'adjoint' or 'tangent'")
+        cfg = with_params(base, theta.detach().cpu().numpy()).replace(precision=FP64)
+        ctx.args = (cfg, steps, average_from, checkpoint_every, mode)
+        ctx.meta = (theta.dtype, theta.device)
+        return theta.new_tensor(nu_average(cfg, steps, average_from))
 
     @staticmethod
     def backward(ctx, grad_out):
-        (g,) = ctx.saved_tensors
-        return grad_out * g, None, None, None
+        cfg, steps, average_from, every, mode = ctx.args
+        if mode == "adjoint":
+            _, g = nu_average_and_gradient_adjoint(cfg, steps, average_from, every)
+        else:
+            _, g = nu_average_and_gradient(cfg, steps, average_from)
+        dtype, device = ctx.meta
+        return grad_out * torch.as_tensor(g, dtype=dtype, device=device), None, None, None, None, None

@@ -167,13 +167,16 @@ def test_full_size_tangent_vs_oracle(mods):
     check_gradient(g, fd, J, th, "full-size oracle-fd")
 
 
-def test_autograd_function(mods, tangent):
+@pytest.mark.parametrize("mode", ["adjoint", "tangent"])
+def test_autograd_function(mods, tangent, mode):
+    """NuTimeAverage: forward gives J of the FP64 run, backward the gradient of the reverse sweep
+    (or of the tangent run), equal to the tangent run's to rounding."""
     import torch
     _, sens = mods
     J, g = tangent
     theta = torch.tensor(sens.params_of(base_case()), dtype=torch.float64, requires_grad=True)
-    out = sens.NuTimeAverage.apply(theta, base_case(), STEPS, AVG_FROM)
+    out = sens.NuTimeAverage.apply(theta, base_case(), STEPS, AVG_FROM, 64, mode)
     (3.0 * out).backward()
     # theta -> config recomputes nu = (tau - 1/2)/3, which may move nu by an ulp
     assert abs(out.item() - J) <= 1e-12 * abs(J)
-    assert np.allclose(theta.grad.numpy(), 3.0 * g, rtol=1e-12, atol=0)
+    assert np.allclose(theta.grad.numpy(), 3.0 * g, rtol=1e-11, atol=0)
