@@ -43,6 +43,8 @@ struct lbm_handle {
     int cap_lbm = 0, cap_th = 0;      // tile-table capacities (largest over the variants)
     std::vector<int> lbm_off, lbm_cnt, th_off, th_cnt;
     int n_lbm = 0, n_th = 0;
+    lbm::DiagBlock *diag_blocks = nullptr;  // diagnostic workgroups, run by run
+    std::vector<int> diag_off, diag_cnt;
     int var[2] = {0, 0};              // launch variant of k_lbm, k_thermal
     bool phase = false;               // some run has phase-dependent transport or a heated wall
     int pf = 0, pt = 0, ph = 0;
@@ -250,8 +252,16 @@ int validate(const lbm_config *c, int n, int *prec, int *rk, lbm_handle *h)
     return LBM_OK;
 }
 
+// rows per diagnostic workgroup of a run: at most kDiagBlocks workgroups, at least ~2048 nodes each
+int diag_rows(const lbm_config &k)
+{
+    const int a = (k.ny + lbm::kDiagBlocks - 1) / lbm::kDiagBlocks, b = (2048 + k.nx - 1) / k.nx;
+    return std::max(1, std::max(a, b));
+}
+int diag_count(const lbm_config &k) { return (k.ny + diag_rows(k) - 1) / diag_rows(k); }
+
 struct Layout {
-    size_t runs_off, tiles_lbm_off, tiles_th_off, total;
+    size_t runs_off, tiles_lbm_off, tiles_th_off, diag_off, total;
     std::vector<size_t> run_off;
     int n_lbm, n_th;
 };
@@ -295,6 +305,9 @@ Layout layout(const lbm_config *c, int n)
     L.runs_off = off; off += align256(sizeof(RunDev) * n);
     L.tiles_lbm_off = off; off += align256(sizeof(Tile) * L.n_lbm);
     L.tiles_th_off = off; off += align256(sizeof(Tile) * L.n_th);
+    int nd = 0;
+    for (int r = 0; r < n; ++r) nd += diag_count(c[r]);
+    L.diag_off = off; off += align256(sizeof(lbm::DiagBlock) * nd);
     for (int r = 0; r < n; ++r) { L.run_off.push_back(off); off += run_bytes(c[r]); }
     L.total = off;
     return L;
@@ -596,6 +609,7 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
     h->runs_dev = (RunDev *)(ws + L.runs_off);
     h->tiles_lbm = (Tile *)(ws + L.tiles_lbm_off);
     h->tiles_th = (Tile *)(ws + L.tiles_th_off);
+    h->diag_blocks = (lbm::DiagBlock *)(ws + L.diag_off);
     h->cap_lbm = L.n_lbm;
     h->cap_th = L.n_th;
     std::vector<std::vector<double>> probes(n_runs);
@@ -668,6 +682,9 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
         R.probes = (const double *)p; p += align256(2 * sizeof(double) * std::max(1, R.np));
         R.partials = (double *)p; p += align256(sizeof(double) * lbm::kDiagBlocks);
         R.acc = (double *)p; p += align256(sizeof(double) * lbm::kAcc);
+        R.nblk = diag_count(k);
+        R.diag_every = k.diag_every;
+        R.check_every = k.check_every;
         R.qtab = qtab_count(R.cyl_r) ? p : nullptr; p += align256(qtab_count(R.cyl_r) * cb);
         h->runs.push_back(R);
 
@@ -702,6 +719,20 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
             delete h;
             return rc;
         }
+    }
+    // diagnostic workgroups: rows of each run in order
+    std::vector<lbm::DiagBlock> dblocks;
+    for (int r = 0; r < n_runs; ++r) {
+        const int rows = diag_rows(cfgs[r]);
+        h->diag_off.push_back((int)dblocks.size());
+        for (int b = 0, y = 0; y < cfgs[r].ny; ++b, y += rows)
+            dblocks.push_back(lbm::DiagBlock{r, y, std::min(cfgs[r].ny, y + rows), b});
+        h->diag_cnt.push_back((int)dblocks.size() - h->diag_off.back());
+    }
+    if ((rc = upload(h->diag_blocks, dblocks.data(), sizeof(lbm::DiagBlock) * dblocks.size()))) {
+        g_create_error = h->err;
+        delete h;
+        return rc;
     }
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -773,16 +804,16 @@ static int enqueue_step(lbm_handle *h, const lbm::Timing *tm = nullptr, bool *th
     for (int r = 0; r < h->n_runs; ++r) {
         const lbm_config &k = h->cfgs[r];
         const bool fon = h->step >= k.warmup_steps;
-        const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
-        const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
-        if (acc || chk) {
-            if (tm && !diag) HIPCHK(h, hipEventRecord(tm[2].start, h->stream));
-            diag = true;
-            HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, h->stream));
-        }
+        diag |= (k.diag_every > 0 && fon && h->step % k.diag_every == 0) || (k.check_every > 0 && h->step % k.check_every == 0);
         thermal |= fon && k.rk_stages > 0;
     }
-    if (tm && diag) HIPCHK(h, hipEventRecord(tm[2].stop, h->stream));
+    if (diag) {
+        // one launch; each run takes part when its sample or check falls on this step
+        if (tm) HIPCHK(h, hipEventRecord(tm[2].start, h->stream));
+        HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, h->diag_blocks, h->diag_off.back() + h->diag_cnt.back(), 0,
+                                   h->n_runs, h->pt, h->step, -1, h->stream));
+        if (tm) HIPCHK(h, hipEventRecord(tm[2].stop, h->stream));
+    }
     if (thermal) {
         HIPCHK(h, lbm::launch_thermal(h->precision, h->rk, h->var[1], h->phase, h->runs_dev, h->tiles_th, h->n_th, h->pt, h->step,
                                       h->stream, tm ? tm + 1 : nullptr));
@@ -808,12 +839,17 @@ static int enqueue_step_groups(lbm_handle *h)
         const int l0 = h->lbm_off[g.run0], l1 = h->lbm_off[g.run1 - 1] + h->lbm_cnt[g.run1 - 1];
         HIPCHK(h, lbm::launch_lbm(h->precision, h->var[0], true, h->phase, h->runs_dev, h->tiles_lbm + l0, l1 - l0, h->pf,
                                   h->pt, h->ph, h->step, g.s));
+        bool diag = false;
         for (int r = g.run0; r < g.run1; ++r) {
             const lbm_config &k = h->cfgs[r];
             const bool fon = h->step >= k.warmup_steps;
-            const bool acc = k.diag_every > 0 && fon && h->step % k.diag_every == 0;
-            const bool chk = k.check_every > 0 && h->step % k.check_every == 0;
-            if (acc || chk) HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, r, h->pt, acc ? 1 : 0, g.s));
+            diag |= (k.diag_every > 0 && fon && h->step % k.diag_every == 0) ||
+                    (k.check_every > 0 && h->step % k.check_every == 0);
+        }
+        if (diag) {
+            const int d0 = h->diag_off[g.run0], d1 = h->diag_off[g.run1 - 1] + h->diag_cnt[g.run1 - 1];
+            HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, h->diag_blocks + d0, d1 - d0, g.run0, g.run1 - g.run0, h->pt,
+                                       h->step, -1, g.s));
         }
         if (thermal) {
             const int t0 = h->th_off[g.run0], t1 = h->th_off[g.run1 - 1] + h->th_cnt[g.run1 - 1];
@@ -1150,7 +1186,8 @@ int lbm_wall_heat_flux(lbm_handle *h, int run, double *q_mean, double *nu, doubl
     int rc = check_run(h, run);
     if (rc) return rc;
     if ((rc = moments_pass(h, run))) return rc;
-    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, h->diag_blocks + h->diag_off[run], h->diag_cnt[run], run, 1,
+                               h->pt, h->step, run, h->stream));
     double acc[8];
     HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1166,7 +1203,8 @@ int lbm_nu_tangent(lbm_handle *h, int run, double *dnu, double *dnu_time_avg)
     if (rc) return rc;
     if (h->precision != LBM_F64_TANGENT) return fail(h, LBM_EINVAL, "the handle does not carry tangents");
     if ((rc = moments_pass(h, run))) return rc;
-    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, h->diag_blocks + h->diag_off[run], h->diag_cnt[run], run, 1,
+                               h->pt, h->step, run, h->stream));
     double acc[lbm::kAcc];
     HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1196,7 +1234,8 @@ int lbm_total_mass(lbm_handle *h, int run, double *mass)
     int rc = check_run(h, run);
     if (rc) return rc;
     if ((rc = moments_pass(h, run))) return rc;
-    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, run, h->pt, 0, h->stream));
+    HIPCHK(h, lbm::launch_diag(h->precision, h->runs_dev, h->diag_blocks + h->diag_off[run], h->diag_cnt[run], run, 1,
+                               h->pt, h->step, run, h->stream));
     double acc[8];
     HIPCHK(h, hipMemcpyAsync(acc, h->runs[run].acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1533,6 +1572,17 @@ int adjoint_supported(lbm_handle *h, int run)
 }
 
 size_t adj_state_bytes(const RunDev &R) { return sizeof(double) * lbm::adjoint_state_doubles(R.nx, R.ny, R.pitch); }
+
+// change a run's Nu sampling period (host launch pattern and the device descriptor)
+int set_run_diag(lbm_handle *h, int run, int every)
+{
+    h->cfgs[run].diag_every = every;
+    h->runs[run].diag_every = every;
+    HIPCHK(h, hipMemcpyAsync(h->runs_dev + run, &h->runs[run], sizeof(RunDev), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    return LBM_OK;
+}
 size_t adj_scratch_bytes(const RunDev &R) { return sizeof(double) * lbm::adjoint_scratch_doubles(R.nx, R.ny, R.pitch); }
 // raw FP64 state of a run in a device slot: f* [9] planes, T plane, outlet history [3][ny]
 size_t state_doubles(const RunDev &R) { return 10 * (size_t)R.ny * R.pitch + 3 * (size_t)R.ny; }
@@ -1625,13 +1675,11 @@ int lbm_nu_gradient(lbm_handle *h, int steps, int average_from, int checkpoint_e
     const long long n0 = h->step;
     const int diag0 = h->cfgs[0].diag_every;
     auto finish = [&](int code) {
-        h->cfgs[0].diag_every = diag0;
-        drop_graphs(h);
-        return code;
+        const int rc2 = set_run_diag(h, 0, diag0);
+        return code ? code : rc2;
     };
     // forward: checkpoints every K steps, Nu sampled every step of the averaging window
-    h->cfgs[0].diag_every = 1;
-    drop_graphs(h);
+    if ((rc = set_run_diag(h, 0, 1))) return finish(rc);
     for (int c = 0; c < nck; ++c) {
         const int s0 = c * K, s1 = std::min(steps, s0 + K);
         if ((rc = copy_state(h, 0, ckpt + (size_t)c * sd, true))) return finish(rc);
@@ -1650,8 +1698,7 @@ int lbm_nu_gradient(lbm_handle *h, int steps, int average_from, int checkpoint_e
     if (J) *J = samples > 0 ? acc[3] / samples : 0.0;
     if ((rc = copy_state(h, 0, fin, true))) return finish(rc);
     // reverse sweep over the segments, each recomputed from its checkpoint
-    h->cfgs[0].diag_every = 0;
-    drop_graphs(h);
+    if ((rc = set_run_diag(h, 0, 0))) return finish(rc);
     HIPCHK(h, hipMemsetAsync(adj[0], 0, sizeof(double) * ad, h->stream));
     int cur = 0;
     for (int c = nck - 1; c >= 0; --c) {

@@ -9,7 +9,7 @@
 namespace lbm {
 
 constexpr int kMaxProbes = 4096;
-constexpr int kDiagBlocks = 256;
+constexpr int kDiagBlocks = 2048;  // most diagnostic workgroups of a run
 // parameter directions of the tangent precision: superheat dTr_wall, u_in, acentric factor, tau
 constexpr int kTangents = 4;
 // FP64 accumulators per run: [0] mass, [1] q_mean, [2] Nu, [3] sum of Nu, [4] count, [5] non-finite,
@@ -51,8 +51,16 @@ struct RunDev {
     void *hist[2];            // outlet history, compute type, [3][ny]
     const double *probes;     // [np][2] probe coordinates
     const void *qtab;         // compute type, [2R+3][2R+3][8] wall fractions of cut links (cyl_r > 0)
-    double *partials;         // [kDiagBlocks] partial mass sums
+    double *partials;         // [kDiagBlocks] partial mass sums of the diagnostic workgroups
     double *acc;              // [kAcc]
+    int nblk;                 // diagnostic workgroups of this run (<= kDiagBlocks)
+    int diag_every, check_every;
+};
+
+// One workgroup of the diagnostic reduction: rows [row0, row1) of run `run`, its index among the
+// run's workgroups.
+struct DiagBlock {
+    int run, row0, row1, index;
 };
 
 // One work item: run index and tile coordinates.
@@ -89,8 +97,11 @@ hipError_t launch_lbm(int precision, int variant, bool write_f, bool phase, cons
                       const Timing *timing = nullptr);
 hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
                           int n_tiles, int parity_t, long long step, hipStream_t stream, const Timing *timing = nullptr);
-hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int parity_t, int accumulate,
-                       hipStream_t stream);
+// Diagnostic reduction (two launches) of runs run0 .. run0 + n_runs - 1 over their workgroups
+// blocks[0 .. n_blocks): with readout < 0 the runs whose Nu sample or finiteness check falls on
+// `step` (accumulating the Nu samples), else a read-out of run `readout`.
+hipError_t launch_diag(int precision, const RunDev *runs_dev, const DiagBlock *blocks, int n_blocks, int run0, int n_runs,
+                       int parity_t, long long step, int readout, hipStream_t stream);
 
 // Reverse-mode adjoint of one FP64 step of run `run` (lbm_adjoint.hip).  Rh: host copy of the run's
 // descriptor.  fs, hist, T: state n; ain / aout: adjoint states of n+1 / n (adjoint_state_doubles);

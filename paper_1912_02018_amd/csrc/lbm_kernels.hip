@@ -1064,29 +1064,9 @@ __global__ __launch_bounds__(NT) void k_thermal_tan(const RunDev *__restrict__ r
 
 
 // ------------------------------------------------------------------------------------------
-// Diagnostics: FP64 mass and wall heat flux, fixed reduction order
+// Diagnostics: FP64 mass and wall heat flux (Sec. IV B), one launch for all runs whose sample falls
+// on this step, fixed reduction order (bitwise reproducible)
 // ------------------------------------------------------------------------------------------
-template <typename C>
-__global__ __launch_bounds__(256) void k_diag_partial(const RunDev *__restrict__ runs, int run)
-{
-    const RunDev &R = runs[run];
-    const gp<const C> rho = gin<C>(R.rho);
-    __shared__ double red[256];
-    double s = 0.0;
-    const long long n = (long long)R.nx * R.ny;
-    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
-        const int x = (int)(k % R.nx), y = (int)(k / R.nx);
-        if (!solid_at(R, x, y)) s += (double)rho[(size_t)y * R.pitch + x];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) R.partials[blockIdx.x] = red[0];
-}
-
 template <typename A> __device__ inline double val(const A &x) { return (double)x; }
 template <typename A> __device__ inline double der(const A &, int) { return 0.0; }
 template <> __device__ inline double der<Dual>(const Dual &x, int k) { return x.d[k]; }
@@ -1097,17 +1077,98 @@ template <typename A> __device__ inline A vapour_alpha(const RunDev &R, const Co
     return R.phase_props ? (A)R.alpha_v : K.alpha;
 }
 
-template <typename C>
-__global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ runs, int run, int pt, int accumulate)
+// sum over the 256 threads of a workgroup in a fixed order: FP64 values across each wavefront by
+// butterfly shuffles, then the four wavefronts' sums in LDS; tangent values by an LDS tree
+template <typename A> __device__ inline A block_sum(A v, A *lds)
 {
-    // FP64 arithmetic; the tangent type carries the derivatives of Nu along
+    if constexpr (std::is_same<A, double>::value) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+        __syncthreads();
+        const A s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+        __syncthreads();
+        return s;
+    } else {
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) lds[threadIdx.x] = lds[threadIdx.x] + lds[threadIdx.x + w];
+            __syncthreads();
+        }
+        const A s = lds[0];
+        __syncthreads();
+        return s;
+    }
+}
+
+// Whether a run's diagnostic takes part in a launch: a read-out of run `readout` (>= 0), or the
+// run's Nu sample (acc) or finiteness check falling on `step`.
+__device__ inline bool diag_fires(const RunDev &R, int run, long long step, int readout, bool &acc)
+{
+    acc = readout < 0 && R.diag_every > 0 && step >= R.warmup && step % R.diag_every == 0;
+    const bool chk = readout < 0 && R.check_every > 0 && step % R.check_every == 0;
+    return readout >= 0 ? run == readout : (acc || chk);
+}
+
+// partial FP64 sums of the density over the rows of each diagnostic workgroup (fluid nodes, row by
+// row, the cylinder's rows with the solid test)
+template <typename C>
+__global__ __launch_bounds__(256) void k_diag_partial(const RunDev *__restrict__ runs, const DiagBlock *__restrict__ blocks,
+                                                      long long step, int readout)
+{
+    const DiagBlock b = blocks[blockIdx.x];
+    const RunDev &R = runs[b.run];
+    bool acc;
+    if (!diag_fires(R, b.run, step, readout, acc)) return;
+    __shared__ double lds[4];
+    const gp<const C> rho = gin<C>(R.rho);
+    // four row positions per thread and pass, loaded before they are summed (their loads overlap)
+    double s = 0.0;
+    const int r2 = R.cyl_r * R.cyl_r;
+    for (int y = b.row0; y < b.row1; ++y) {
+        const gp<const C> row = rho + (size_t)y * R.pitch;
+        const int dy = y - R.cyl_y;
+        const bool cut = R.cyl_r > 0 && dy * dy <= r2;
+        for (int x0 = threadIdx.x; x0 < R.nx; x0 += 1024) {
+            C v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = min(x0 + 256 * j, R.nx - 1);
+                v[j] = row[x];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = x0 + 256 * j, dx = x - R.cyl_x;
+                const bool take = x < R.nx && !(cut && dx * dx + dy * dy <= r2);
+                s += take ? (double)v[j] : 0.0;
+            }
+        }
+    }
+    s = block_sum<double>(s, lds);
+    if (threadIdx.x == 0) R.partials[b.index] = s;
+}
+
+// one workgroup per run: the partial sums in their fixed order, the wall probes (q_p, Nu), the
+// accumulators
+template <typename C>
+__global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ runs, int run0, int pt, long long step,
+                                                    int readout)
+{
     using A = typename std::conditional<is_dual<C>, Dual, double>::type;
-    constexpr int NQ = is_dual<C> ? kMaxTangentProbes : kMaxProbes;
+    const int run = run0 + blockIdx.x;
     const RunDev &R = runs[run];
+    bool acc;
+    if (!diag_fires(R, run, step, readout, acc)) return;
+    __shared__ A lds[is_dual<C> ? 256 : 4];
+    __shared__ double ldsd[4];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < R.nblk; k += 256) m += R.partials[k];
+    const double mass = block_sum<double>(m, ldsd);
     const Consts<A> K(R);
     const gp<const C> rho = gin<C>(R.rho);
     const gp<const C> T = gin<C>(R.T[pt]);
-    __shared__ A qp[NQ];
+    A qs = 0.0;
     for (int k = threadIdx.x; k < R.np; k += 256) {
         const double px = R.probes[2 * k], py = R.probes[2 * k + 1];
         const int x0 = (int)floor(px), y0 = (int)floor(py);
@@ -1117,14 +1178,10 @@ __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ r
         const A r = w00 * (A)rho[i00] + w10 * (A)rho[i00 + 1] + w01 * (A)rho[i01] + w11 * (A)rho[i01 + 1];
         const A tp = w00 * (A)T[i00] + w10 * (A)T[i00 + 1] + w01 * (A)T[i01] + w11 * (A)T[i01 + 1];
         A dal;
-        qp[k] = r * (A)R.cv * alpha_at<!is_dual<C>>(R, K, r, dal) * (K.T_w - tp) / (A)1.5;
+        qs = qs + r * (A)R.cv * alpha_at<!is_dual<C>>(R, K, r, dal) * (K.T_w - tp) / (A)1.5;
     }
-    __syncthreads();
+    A q = block_sum<A>(qs, lds);
     if (threadIdx.x == 0) {
-        double mass = 0.0;
-        for (int b = 0; b < kDiagBlocks; ++b) mass += R.partials[b];
-        A q = 0.0;
-        for (int k = 0; k < R.np; ++k) q = q + qp[k];
         q = R.np > 0 ? q / (A)(double)R.np : (A)0.0;
         const A dT = K.T_w - K.T_sat;
         const A nu = (R.np > 0 && val(dT) != 0.0)
@@ -1134,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_diag_final(const RunDev *__restrict__ r
         R.acc[1] = val(q);
         R.acc[2] = val(nu);
         for (int k = 0; k < kTangents; ++k) R.acc[8 + k] = der(nu, k);
-        if (accumulate) {
+        if (acc) {
             R.acc[3] += val(nu);
             R.acc[4] += 1.0;
             for (int k = 0; k < kTangents; ++k) R.acc[12 + k] += der(nu, k);
@@ -1342,17 +1399,19 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
     }
 }
 
-hipError_t launch_diag(int precision, const RunDev *runs_dev, int run, int pt, int accumulate, hipStream_t stream)
+hipError_t launch_diag(int precision, const RunDev *runs_dev, const DiagBlock *blocks, int n_blocks, int run0, int n_runs,
+                       int pt, long long step, int readout, hipStream_t stream)
 {
+    if (n_blocks <= 0 || n_runs <= 0) return hipSuccess;
     if (precision == 4) {
-        k_diag_partial<Dual><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
-        k_diag_final<Dual><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
+        k_diag_partial<Dual><<<n_blocks, 256, 0, stream>>>(runs_dev, blocks, step, readout);
+        k_diag_final<Dual><<<n_runs, 256, 0, stream>>>(runs_dev, run0, pt, step, readout);
     } else if (precision == 0) {
-        k_diag_partial<double><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
-        k_diag_final<double><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
+        k_diag_partial<double><<<n_blocks, 256, 0, stream>>>(runs_dev, blocks, step, readout);
+        k_diag_final<double><<<n_runs, 256, 0, stream>>>(runs_dev, run0, pt, step, readout);
     } else {
-        k_diag_partial<float><<<kDiagBlocks, 256, 0, stream>>>(runs_dev, run);
-        k_diag_final<float><<<1, 256, 0, stream>>>(runs_dev, run, pt, accumulate);
+        k_diag_partial<float><<<n_blocks, 256, 0, stream>>>(runs_dev, blocks, step, readout);
+        k_diag_final<float><<<n_runs, 256, 0, stream>>>(runs_dev, run0, pt, step, readout);
     }
     return hipGetLastError();
 }
