@@ -348,6 +348,175 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
 }
 
 // ------------------------------------------------------------------------------------------
+// k_lbm_strip: the same step for a strip of NT - 4 columns marching down a chunk of CH rows
+// ------------------------------------------------------------------------------------------
+// Lane l owns column x0 - 2 + l.  An iteration forms the pulls, moments and psi of 4 rows q .. q + 3
+// (all lanes: the strip and 2 halo columns on each side; every pull of the 4 rows is issued before
+// the first is used) and collides rows q - 2 .. q + 1 (the strip's columns) with the psi of rows
+// q - 4 .. q + 3 from a ring of 12 LDS rows, so that every position's pulls and psi are formed once
+// per chunk instead of once per tile that reaches it (a 64 x 8 tile forms psi on 68 x 12 positions).
+// One barrier per iteration: the ring holds the rows the collision reads plus the 4 written next.
+// The per-node arithmetic is that of k_lbm, so both give the same bits.
+template <typename C> __device__ inline PairD<C> pair_diffs_rows(const C *const rows[5], int c)
+{
+#define W_(dx, dy) rows[2 + (dy)][c + (dx)]
+    PairD<C> d;
+    d.d10 = W_(1, 0) - W_(-1, 0);
+    d.d01 = W_(0, 1) - W_(0, -1);
+    d.d11 = W_(1, 1) - W_(-1, -1);
+    d.d1m = W_(1, -1) - W_(-1, 1);
+    d.d20 = W_(2, 0) - W_(-2, 0);
+    d.d02 = W_(0, 2) - W_(0, -2);
+    d.d21 = W_(2, 1) - W_(-2, -1);
+    d.d2m = W_(2, -1) - W_(-2, 1);
+    d.d12 = W_(1, 2) - W_(-1, -2);
+    d.d1m2 = W_(1, -2) - W_(-1, 2);
+    d.d22 = W_(2, 2) - W_(-2, -2);
+    d.d2m2 = W_(2, -2) - W_(-2, 2);
+#undef W_
+    return d;
+}
+
+template <typename S, int NT, int CH, bool WRITE_F, bool PH, int OCC = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void k_lbm_strip(
+    const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pf, int pt, int ph, long long step)
+{
+    using C = CT<S>;
+    constexpr int W = NT - 4, RB = 4, RING = 3 * RB;
+    static_assert(CH % RB == 0, "chunks are whole groups of rows");
+    __shared__ C s_psi[RING][NT];
+
+    const Tile t = tiles[blockIdx.x];
+    const RunDev &R = runs[t.run];
+    const Consts<C> K(R);
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    const bool fon = step >= R.warmup;
+    const char *fin = (const char *)R.f[pf];
+    char *fout = (char *)R.f[pf ^ 1];
+    const gp<C> hout = gout<C>(R.hist[ph ^ 1]);
+    const int lane = threadIdx.x;
+    const int gx = t.tx * W - 2 + lane;
+    const bool own_col = lane >= 2 && lane < NT - 2 && gx < nx;
+    const int y0 = t.ty * CH, y1 = min(ny, y0 + CH);
+    const unsigned plane = (unsigned)ny * P;
+    // the kind of a position and its mapped column depend on the column only
+    int rx, ry_;
+    const int kind = map_pos<PH>(R, gx, 0, rx, ry_);
+
+    // iteration: rows q .. q + RB - 1 (pulls, moments, psi; all lanes), then rows q - 2 .. q + RB - 3
+    // (force and collision; the strip's columns) with the psi of rows q - 4 .. q + RB - 1.  The raw
+    // moments (rho, jx, jy, sum f (cx^2 - cy^2), sum f cx cy) stay with the lane that formed them: rows
+    // q, q + 1 are collided in the same iteration, rows q + 2, q + 3 in the next (mprev).
+    C mprev[2][5] = {};
+    for (int q = y0 - 2, it = 0; q - 2 < y1; q += RB, ++it) {
+        C mcur[RB][5] = {};
+        C f[RB][9], Tv[RB];
+        unsigned skip = 0;   // bit j: row q + j forms nothing (outside the chunk's reach, or solid)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int y = q + j;
+            const bool own_row = y >= y0 && y < y1;
+            const int ry = wrap(y, ny);
+            if (y >= y1 + 2 || !(fon || (own_col && own_row)) || kind == WALL_GHOST || solid_at(R, rx, ry)) {
+                skip |= 1u << j;
+                continue;
+            }
+            pull_bulk<S, C, PH>(R, K, fin, rx, ry, f[j]);
+            Tv[j] = ld_at<C>(R.T[pt], (unsigned)(ry * P + rx));
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int y = q + j;
+            const bool own_row = y >= y0 && y < y1;
+            if (y >= y1 + 2 || !(fon || (own_col && own_row))) continue;
+            const int ry = wrap(y, ny);
+            C rho, T, m[5];
+            if ((skip >> j) & 1u) {
+                rho = K.rho_w;
+                T = K.T_w;
+                m[0] = rho; m[1] = 0; m[2] = 0; m[3] = 0; m[4] = 0;
+            } else {
+                C *fj = f[j];
+                if (near_cylinder(R, rx, ry) || (R.bc_x != 0 && (rx == 0 || rx == nx - 1)))
+                    fix_special<S, C, PH>(R, K, fin, R.hist[ph], rx, ry, fj);
+                rho = ((fj[0] + fj[1]) + (fj[2] + fj[3])) + ((fj[4] + fj[5]) + (fj[6] + fj[7])) + fj[8];
+                T = kind == INLET_GHOST ? K.T_sat : Tv[j];
+                m[0] = rho;
+                m[1] = (fj[1] - fj[2]) + (fj[5] - fj[6]) + (fj[7] - fj[8]);
+                m[2] = (fj[3] - fj[4]) + (fj[5] - fj[6]) + (fj[8] - fj[7]);
+                m[3] = (fj[1] + fj[2]) - (fj[3] + fj[4]);
+                m[4] = (fj[5] + fj[6]) - (fj[7] + fj[8]);
+                if (WRITE_F && own_col && own_row && R.bc_x != 0 && gx == nx - 1) {
+                    hout[0 * ny + y] = fj[2];
+                    hout[1 * ny + y] = fj[6];
+                    hout[2 * ny + y] = fj[8];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) mcur[j][k] = m[k];
+            if (fon) s_psi[(it % 3) * RB + j][lane] = pseudopotential(K, rho, T);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int r = q - 2 + j;
+            if (r < y0 || r >= y1 || !own_col) continue;
+            const unsigned idx = (unsigned)(r * P + gx);
+            if (solid_at(R, gx, r)) {
+                *at<C>(R.rho, idx) = K.rho_w;
+                *at<C>(R.ux, idx) = 0;
+                *at<C>(R.uy, idx) = 0;
+                if (WRITE_F) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        *(gp<RawT<S>>)(fout + ((unsigned)i * plane + idx) * (unsigned)sizeof(RawT<S>)) =
+                            Conv<S>::st((C)lat_w(i) * K.rho_w, K.shiftw[i]);
+                }
+                continue;
+            }
+            // row r was formed in this iteration (j >= 2) or in the previous one (j < 2)
+            const C *mr = j >= 2 ? mcur[j - 2] : mprev[j];
+            const C rho = mr[0], jx = mr[1], jy = mr[2], m4 = mr[3], m5 = mr[4];
+            C Fx = 0, Fy = 0, A = 0;
+            if (fon) {
+                // psi of rows r - 2 .. r + 2: the ring slot of row q + i is ((it + (i < 0 ? -1 : 0)) mod 3) RB + i mod RB
+                const C *rows[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const int i = j - 4 + k;   // row r - 2 + k = q + i, i in -4 .. RB - 1
+                    const int itr = i < 0 ? it - 1 : it;
+                    rows[k] = s_psi[(itr % 3) * RB + (i < 0 ? i + RB : i)];
+                }
+                const PairD<C> d = pair_diffs_rows(rows, lane);
+                const C psi0 = rows[2][lane];
+                // F_m = -G cs^2 psi sum_k w_k psi(x + e_k) e_k (eq. interForce); G cs^2 = 2/psi_scale
+                const C pre = -(C)2 * Ar<C>::rcp(K.psi_scale) * psi0;
+                const C Fmx = pre * d.gx();
+                const C Fmy = pre * d.gy();
+                A = (C)2 * K.sigma * (Fmx * Fmx + Fmy * Fmy) * Ar<C>::rcp(psi0 * psi0);
+                Fx = Fmx + (rho - K.rho_gref) * K.gx;
+                Fy = Fmy + (rho - K.rho_gref) * K.gy;
+            }
+            C U, V, fs[9];
+            collide_node<C>(rho, jx, jy, m4, m5, Fx, Fy, A, omega_at<PH>(R, K, rho), U, V, fs);
+            *at<C>(R.rho, idx) = rho;
+            *at<C>(R.ux, idx) = U;
+            *at<C>(R.uy, idx) = V;
+            if (!WRITE_F) continue;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                *(gp<RawT<S>>)(fout + ((unsigned)i * plane + idx) * (unsigned)sizeof(RawT<S>)) =
+                    Conv<S>::st(fs[i], K.shiftw[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            mprev[0][k] = mcur[2][k];
+            mprev[1][k] = mcur[3][k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // k_thermal: Runge-Kutta update of the temperature equation (eq. energy) for one tile
 // ------------------------------------------------------------------------------------------
 // The frozen fields rho, u and T^n are loaded with a halo of 2 nodes per stage, so the stages
@@ -1251,7 +1420,9 @@ __global__ __launch_bounds__(256) void k_init(const RunDev *__restrict__ runs, i
 // ------------------------------------------------------------------------------------------
 // stream+collide: FP32 and reduced-precision storage / FP64
 static const Variant kLbm32[] = {{32, 16, 256, 0}, {64, 16, 512, 0}, {32, 32, 512, 0}, {32, 8, 256, 0},
-                                 {32, 8, 256, 6},  {64, 8, 512, 6},  {64, 8, 512, 7}};
+                                 {32, 8, 256, 6},  {64, 8, 512, 6},  {64, 8, 512, 7},
+                                 // strips (k_lbm_strip): NT - 4 columns by a chunk of rows
+                                 {124, 64, 128, 0}, {252, 32, 256, 0}, {60, 32, 64, 0}, {60, 64, 64, 0}};
 static const Variant kLbm64[] = {{32, 16, 256, 0}, {16, 16, 256, 0}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage); 64 x 32 with 512
 // threads also with a register budget of 4 waves per SIMD, which gives it a second workgroup per CU
@@ -1266,7 +1437,7 @@ static const Variant kTanTh[] = {{16, 8, 256, 0}};
 int variant_count(int precision, int kernel)
 {
     if (precision == 4) return 1;
-    if (kernel == 0) return precision == 0 ? 2 : 7;
+    if (kernel == 0) return precision == 0 ? 2 : 11;
     return precision == 0 ? 2 : 5;
 }
 
@@ -1307,6 +1478,25 @@ static hipError_t lbm_go(bool write_f, bool phase, const RunDev *runs, const Til
     return hipGetLastError();
 }
 
+template <typename S, int NT, int CH, int OCC = 0>
+static hipError_t strip_go(bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf, int pt,
+                           int ph, long long step, hipStream_t st, const Timing *tm)
+{
+    constexpr bool kPhase = std::is_same<S, float>::value || std::is_same<S, double>::value;
+    if constexpr (kPhase) {
+        if (phase) {
+            if (write_f) dispatch(k_lbm_strip<S, NT, CH, true, true, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+            else dispatch(k_lbm_strip<S, NT, CH, false, true, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+            return hipGetLastError();
+        }
+    } else {
+        if (phase) return hipErrorInvalidValue;
+    }
+    if (write_f) dispatch(k_lbm_strip<S, NT, CH, true, false, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+    else dispatch(k_lbm_strip<S, NT, CH, false, false, OCC>, n, NT, st, tm, runs, tiles, pf, pt, ph, step);
+    return hipGetLastError();
+}
+
 template <typename S>
 static hipError_t lbm_impl(int v, bool write_f, bool phase, const RunDev *runs, const Tile *tiles, int n, int pf,
                            int pt, int ph, long long step, hipStream_t st, const Timing *tm)
@@ -1330,6 +1520,10 @@ static hipError_t lbm_impl(int v, bool write_f, bool phase, const RunDev *runs, 
         case 4: return lbm_go<S, 32, 8, 256, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
         case 5: return lbm_go<S, 64, 8, 512, 6>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
         case 6: return lbm_go<S, 64, 8, 512, 7>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 7: return strip_go<S, 128, 64>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 8: return strip_go<S, 256, 32>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 9: return strip_go<S, 64, 32>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
+        case 10: return strip_go<S, 64, 64>(write_f, phase, runs, tiles, n, pf, pt, ph, step, st, tm);
         default: return hipErrorInvalidValue;
         }
     }
