@@ -252,7 +252,9 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
 
 /* Launch variants of the stencil kernels (kernel 0: k_lbm, 1: k_thermal): each is a tile of
  * tx x ty nodes per workgroup of `threads` threads, compiled with a register budget for min_waves
- * waves per SIMD if min_waves > 0 (any output pointer may be NULL).  lbm_set_variant rebuilds the tile tables
+ * waves per SIMD if min_waves > 0 (any output pointer may be NULL).  A temperature variant with
+ * ty = 0 is a strip of tx columns marching down a chunk of rows whose length is chosen when the tile
+ * tables are built, so that one launch spreads over the workgroups the GPU holds at once.  lbm_set_variant rebuilds the tile tables
  * (waits for the stream); lbm_autotune times every variant of both kernels on the handle's
  * current state with HIP events (`launches` launches each, 20 if 0) and keeps the fastest, writing
  * the chosen indices to best[2] if not NULL.  Every tuning is remembered for the rest of the process

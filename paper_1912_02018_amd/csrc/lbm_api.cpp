@@ -66,7 +66,7 @@ struct lbm_handle {
     // lbm_create_static: the workspace is the device's static array, valid until the next
     // lbm_create_static on that device (generation `gen`)
     bool static_ws = false;
-    int device = -1;
+    int device = -1;  // the device current at creation
     unsigned long long gen = 0;
     std::string err;
 };
@@ -284,10 +284,23 @@ size_t run_bytes(const lbm_config &k)
     return b;
 }
 
+// rows of the chunks of a chunked variant: ty rounded up to a whole number of ring periods (8 rows),
+// or for ty = 0 the run's rows split into n_chunks
+int chunk_rows(const lbm::Variant &v, int ny, int n_chunks)
+{
+    const int ch = v.ty > 0 ? v.ty : (ny + n_chunks - 1) / n_chunks;
+    return std::max(8, (ch + 7) / 8 * 8);
+}
+
+// tiles of a variant over the runs (for a chunked variant whose chunks are sized at build time, the
+// most there can be: chunks of 8 rows)
 int tile_count(const lbm_config *c, int n, lbm::Variant v)
 {
     int t = 0;
-    for (int r = 0; r < n; ++r) t += ((c[r].nx + v.tx - 1) / v.tx) * ((c[r].ny + v.ty - 1) / v.ty);
+    for (int r = 0; r < n; ++r) {
+        const int ty = v.chunked ? chunk_rows(v, c[r].ny, (c[r].ny + 7) / 8) : v.ty;
+        t += ((c[r].nx + v.tx - 1) / v.tx) * ((c[r].ny + ty - 1) / ty);
+    }
     return t;
 }
 
@@ -446,11 +459,28 @@ int build_tiles(lbm_handle *h)
         std::vector<int> &cnt = k == 0 ? h->lbm_cnt : h->th_cnt;
         off.clear();
         cnt.clear();
+        // chunks sized to the launch: the workgroups the GPU holds at once, shared among the runs in
+        // proportion to their nodes, each run's strips taking an equal number of chunks
+        double resident = 0.0, nodes = 0.0;
+        if (v.chunked && v.ty == 0) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) cus = 0;
+            resident = (double)cus * lbm::chunked_blocks_per_cu(h->precision, h->var[k], h->rk, h->phase);
+            for (int r = 0; r < h->n_runs; ++r) nodes += (double)h->runs[r].nx * h->runs[r].ny;
+        }
         for (int r = 0; r < h->n_runs; ++r) {
             const RunDev &R = h->runs[r];
             off.push_back((int)tl[k].size());
-            for (int ty = 0; ty < (R.ny + v.ty - 1) / v.ty; ++ty)
-                for (int tx = 0; tx < (R.nx + v.tx - 1) / v.tx; ++tx) tl[k].push_back(Tile{r, tx, ty, 0});
+            const int strips = (R.nx + v.tx - 1) / v.tx;
+            if (v.chunked) {
+                const double share = resident * ((double)R.nx * R.ny / std::max(nodes, 1.0)) / strips;
+                const int ch = chunk_rows(v, R.ny, std::max(1, std::min((R.ny + 7) / 8, (int)share)));
+                for (int y0 = 0; y0 < R.ny; y0 += ch)
+                    for (int tx = 0; tx < strips; ++tx) tl[k].push_back(Tile{r, tx, y0, ch});
+            } else {
+                for (int ty = 0; ty < (R.ny + v.ty - 1) / v.ty; ++ty)
+                    for (int tx = 0; tx < strips; ++tx) tl[k].push_back(Tile{r, tx, ty, 0});
+            }
             cnt.push_back((int)tl[k].size() - off.back());
             // stream-and-collide tiles whose region (tile + the 2-node psi halo) meets the cut-link box or
             // the outlet column (whose convective condition reads the outlet history after the pulls)
@@ -594,6 +624,7 @@ static int create_impl(const lbm_config *cfgs, int n_runs, void *dev_workspace, 
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
 
     lbm_handle *h = new lbm_handle();
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     if (static_device >= 0) {
         std::lock_guard<std::mutex> lock(g_static_mu);
         h->static_ws = true;

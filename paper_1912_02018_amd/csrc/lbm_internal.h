@@ -72,10 +72,16 @@ struct Tile {
 struct Variant {
     int tx, ty, nt;
     int min_waves;  // > 0: compiled with a register budget for this many waves per SIMD
+    // 1: a strip of tx columns marching down a chunk of rows; its tile entry carries the chunk's
+    // first row (ty) and row count (pad, a multiple of 8): ty rows, or with ty = 0 as many as spread
+    // the strips of a launch over the workgroups the GPU holds at once
+    int chunked;
 };
 
 // kernel: 0 = stream+collide (k_lbm), 1 = temperature update (k_thermal)
 int variant_count(int precision, int kernel);
+// workgroups of a chunked temperature variant that one CU holds at once (0 if not chunked)
+int chunked_blocks_per_cu(int precision, int variant, int rk, bool phase);
 Variant variant_shape(int precision, int kernel, int v);
 
 // Start / stop events filled in by a kernel's own dispatch (timing inside the step sequence).

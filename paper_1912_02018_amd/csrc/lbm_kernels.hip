@@ -587,6 +587,126 @@ template <typename C> __device__ inline C grad_y(const RowQ<C> *q)
            (C)W5 * (q[3].s2 - q[1].s2) + (C)(2 * W5) * (q[4].s1 - q[0].s1) + (C)(2 * W8) * (q[4].s2 - q[0].s2);
 }
 
+// Coefficients of L(Y) at the two nodes of a slot ([n]: upper / lower; 8 per node): u/12, v/12
+// and |u| c_d, |v| c_d of the upwind convection, the density-gradient coefficients gx, gy, the
+// centre coefficient c0 (the Laplacian's and the convection's centre weights and the linear part c1
+// of the source) and c2 of sqrt(Y)
+template <typename C, bool PH> struct ThCoef {
+    C u12[2], v12[2], au[2], av[2], gx[2], gy[2], c0[2], c2[2];
+    C al[PH ? 2 : 1];  // alpha at the node (phase-dependent properties)
+};
+
+// Stage-invariant coefficients of both nodes of a slot from the 6 x 5 windows of rho, u_x and u_y
+// (rr[k], ru[k], rv[k]: column -2 of window row k, rows -2 .. 3 of the upper node).  Bit n of hj
+// marks a solid node, whose coefficients are left as they are.  The windows are read one field at a
+// time (its window, then the stencils it feeds), which bounds the registers they hold.
+//   gx, gy = alpha grad(rho)/rho;  source(T) = c1 T + c2 sqrt(T) with
+//   D = div(u)/(rho cv), c1 = -D R rho/(1 - b rho) + B D a rho^2/(1 + 2 b rho - b^2 rho^2),
+//   c2 = A D a rho^2/(1 + 2 b rho - b^2 rho^2), phi'(T) = A/sqrt(T) + B
+template <typename C, bool PH>
+__device__ __forceinline__ void thermal_coef(const RunDev &R, const Consts<C> &K, const C *const rr[6],
+                                             const C *const ru[6], const C *const rv[6], unsigned hj, C cd,
+                                             ThCoef<C, PH> &f)
+{
+    C rho[2], gxr[2], gyr[2], u[2], v[2], div[2];
+    {
+        RowQ<C> q[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) q[k] = row_q(rr[k]);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            rho[n] = q[n + 2].h0;
+            gxr[n] = grad_x(q + n);
+            gyr[n] = grad_y(q + n);
+        }
+    }
+    {
+        RowQ<C> q[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) q[k] = row_q(ru[k]);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            u[n] = q[n + 2].h0;
+            div[n] = grad_x(q + n);
+        }
+    }
+    {
+        RowQ<C> q[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) q[k] = row_q(rv[k]);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            v[n] = q[n + 2].h0;
+            div[n] = div[n] + grad_y(q + n);
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        if ((hj >> n) & 1u) continue;
+        const C ir = Ar<C>::rcp(rho[n]);
+        // (1/(rho cv)) div(lambda grad T) with lambda = rho cv alpha(rho):
+        //   alpha (lap T + grad rho . grad T / rho) + alpha'(rho) grad rho . grad T
+        C dal;
+        const C al = alpha_at<PH>(R, K, rho[n], dal);
+        const C gcoef = al * ir + dal;
+        const C gx = gcoef * gxr[n];
+        const C gy = gcoef * gyr[n];
+        const C D = div[n] * ir * K.inv_cv;
+        const C d1 = (C)1 - K.b * rho[n];
+        const C d2 = (C)1 + (C)2 * K.b * rho[n] - K.b * K.b * rho[n] * rho[n];
+        const C A2 = D * K.a * rho[n] * rho[n] * Ar<C>::rcp(d2);
+        const C c1 = -D * rho[n] * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
+        f.c2[n] = K.dphi_A * A2;
+        // third-order upwind-biased convection per axis:
+        //   u (8 d1 - d2) / 12 + |u| c_d (S2 - 4 S1 + 6 Y)   (d, S: differences / sums of the pair)
+        const C au = absval(u[n]) * cd, av = absval(v[n]) * cd;
+        f.gx[n] = gx;
+        f.gy[n] = gy;
+        if constexpr (PH) f.al[n] = al;
+        f.u12[n] = u[n] * (C)(1.0 / 12.0);
+        f.v12[n] = v[n] * (C)(1.0 / 12.0);
+        f.au[n] = au;
+        f.av[n] = av;
+        f.c0[n] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
+    }
+}
+
+// right-hand side L(Y) of eq. energy at both nodes of a slot with coefficients f, from the 6 x 5
+// window of the stage input (rows[r]: column -2 of window row r, rows -2 .. 3 of the upper node)
+template <typename C, bool PH>
+__device__ __forceinline__ void thermal_rhs(const C *const rows[6], const Consts<C> &K, const ThCoef<C, PH> &f,
+                                            bool phase, C k[2])
+{
+    RowQ<C> q[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) q[r] = row_q(rows[r]);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const RowQ<C> *w = q + n;  // rows -2 .. 2 of node n
+        const C y0 = w[2].h0;
+        // sums and differences of the column's opposite neighbours
+        const C S1 = w[3].h0 + w[1].h0, S2 = w[4].h0 + w[0].h0;
+        const C D1 = w[3].h0 - w[1].h0, D2 = w[4].h0 - w[0].h0;
+        // Laplacian without its centre term: 2 alpha sum_k w_k Y(x + e_k), by weight class
+        const C l1 = w[2].s1 + S1, l4 = w[2].s2 + S2, l2 = w[3].s1 + w[1].s1;
+        const C l5 = (w[3].s2 + w[1].s2) + (w[4].s1 + w[0].s1), l8 = w[4].s2 + w[0].s2;
+        // (a run without phase-dependent properties takes the same arithmetic in either launch,
+        // so batching it with runs that have them does not change its result)
+        C lap;
+        if (PH && phase)
+            lap = f.al[PH ? n : 0] * ((C)(2 * W1) * l1 + (C)(2 * W4) * l4 + (C)(2 * W2) * l2 + (C)(2 * W5) * l5 +
+                                      (C)(2 * W8) * l8);
+        else
+            lap = K.alpha2w1 * l1 + K.alpha2w4 * l4 + K.alpha2w2 * l2 + K.alpha2w5 * l5 + K.alpha2w8 * l8;
+        // third-order upwind-biased convection without its centre term
+        const C conv = f.u12[n] * ((C)8 * w[2].d1 - w[2].d2) + f.au[n] * (w[2].s2 - (C)4 * w[2].s1) +
+                       f.v12[n] * ((C)8 * D1 - D2) + f.av[n] * (S2 - (C)4 * S1);
+        // centre: Laplacian, convection and the linear part of the pressure-work source
+        // T (c1 + c2 phi'(T)), phi'(T) = A / sqrt(T) + B
+        k[n] = (lap - conv) + f.gx[n] * grad_x(w) + f.gy[n] * grad_y(w) + f.c0[n] * y0 + f.c2[n] * Ar<C>::sqrt_(y0);
+    }
+}
+
 template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     using G = ThGeom<TX, TY, NS>;
     static constexpr int H = G::H, RW = G::RW, RN = G::RN, NSLOT = G::NSLOT;
@@ -597,14 +717,7 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     struct Smem {
         C Y[RN], rho[RN], ux[RN], uy[RN];
     };
-    // coefficients of L(Y) at the two nodes of a slot ([n]: upper / lower; 8 registers per node):
-    // u/12, v/12 and |u| c_d, |v| c_d of the upwind convection, the density-gradient coefficients
-    // gx, gy, the centre coefficient c0 (the Laplacian's and the convection's centre weights and the
-    // linear part c1 of the source) and c2 of sqrt(Y)
-    struct Coef {
-        C u12[2], v12[2], au[2], av[2], gx[2], gy[2], c0[2], c2[2];
-        C al[PH ? 2 : 1];  // alpha at the node (phase-dependent properties)
-    };
+    using Coef = ThCoef<C, PH>;
     // When a thread's last slot lies outside every stage after the first (the outer ring of a tile
     // with few threads), that slot forms its stage-1 k together with its invariants and keeps only
     // that, not its coefficients
@@ -683,35 +796,10 @@ template <typename C, int TX, int TY, int NS, int NT, bool PH> struct Thermal {
     {
         // the 6 x 5 window read as positive offsets from its lowest corner
         const C *b = Y + opaque_index(c - 2 * RW - 2);
-        RowQ<C> q[6];
+        const C *rows[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) q[r] = row_q(b + r * RW);
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-            const RowQ<C> *w = q + n;  // rows -2 .. 2 of node n
-            const C y0 = w[2].h0;
-            // sums and differences of the column's opposite neighbours
-            const C S1 = w[3].h0 + w[1].h0, S2 = w[4].h0 + w[0].h0;
-            const C D1 = w[3].h0 - w[1].h0, D2 = w[4].h0 - w[0].h0;
-            // Laplacian without its centre term: 2 alpha sum_k w_k Y(x + e_k), by weight class
-            const C l1 = w[2].s1 + S1, l4 = w[2].s2 + S2, l2 = w[3].s1 + w[1].s1;
-            const C l5 = (w[3].s2 + w[1].s2) + (w[4].s1 + w[0].s1), l8 = w[4].s2 + w[0].s2;
-            // (a run without phase-dependent properties takes the same arithmetic in either launch,
-            // so batching it with runs that have them does not change its result)
-            C lap;
-            if (PH && phase)
-                lap = f.al[PH ? n : 0] * ((C)(2 * W1) * l1 + (C)(2 * W4) * l4 + (C)(2 * W2) * l2 +
-                                             (C)(2 * W5) * l5 + (C)(2 * W8) * l8);
-            else
-                lap = K.alpha2w1 * l1 + K.alpha2w4 * l4 + K.alpha2w2 * l2 + K.alpha2w5 * l5 + K.alpha2w8 * l8;
-            // third-order upwind-biased convection without its centre term
-            const C conv = f.u12[n] * ((C)8 * w[2].d1 - w[2].d2) + f.au[n] * (w[2].s2 - (C)4 * w[2].s1) +
-                           f.v12[n] * ((C)8 * D1 - D2) + f.av[n] * (S2 - (C)4 * S1);
-            // centre: Laplacian, convection and the linear part of the pressure-work source
-            // T (c1 + c2 phi'(T)), phi'(T) = A / sqrt(T) + B
-            k[n] = (lap - conv) + f.gx[n] * grad_x(w) + f.gy[n] * grad_y(w) + f.c0[n] * y0 +
-                   f.c2[n] * Ar<C>::sqrt_(y0);
-        }
+        for (int r = 0; r < 6; ++r) rows[r] = b + r * RW;
+        thermal_rhs<C, PH>(rows, K, f, phase, k);
     }
 
     // stage s: k = L(Y) on the slots of the tile grown by 2 (NS - s), then the next stage input.
@@ -814,10 +902,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
     else Th::template load_region<false>(sm, R, K, rx0, ry0, pt);
     __syncthreads();
 
-    // slots and their stage-invariant coefficients:
-    //   gx, gy = alpha grad(rho)/rho;  source(T) = c1 T + c2 sqrt(T) with
-    //   D = div(u)/(rho cv), c1 = -D R rho/(1 - b rho) + B D a rho^2/(1 + 2 b rho - b^2 rho^2),
-    //   c2 = A D a rho^2/(1 + 2 b rho - b^2 rho^2), phi'(T) = A/sqrt(T) + B
+    // slots and their stage-invariant coefficients (thermal_coef)
     const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
     const int out_c = (nx - 1) - (x0 - H);  // LDS column of the last domain column
     const bool phase = PH && R.phase_props;
@@ -860,69 +945,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
         const int c = kind == OUTLET_GHOST ? ly * RW + out_c : p;
         S.pos[j] |= (unsigned)c << 16;
         const int corner = opaque_index(c - 2 * RW - 2);
-        // one field at a time (its 6 x 5 window, then the stencils it feeds), which bounds the
-        // registers the windows hold beside the slots' coefficients
-        C rho[2], gxr[2], gyr[2], u[2], v[2], div[2];
-        {
-            RowQ<C> q[6];
+        const C *rr[6], *ru[6], *rv[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.rho + corner + k * RW);
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                rho[n] = q[n + 2].h0;
-                gxr[n] = grad_x(q + n);
-                gyr[n] = grad_y(q + n);
-            }
+        for (int k = 0; k < 6; ++k) {
+            rr[k] = sm.rho + corner + k * RW;
+            ru[k] = sm.ux + corner + k * RW;
+            rv[k] = sm.uy + corner + k * RW;
         }
-        {
-            RowQ<C> q[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.ux + corner + k * RW);
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                u[n] = q[n + 2].h0;
-                div[n] = grad_x(q + n);
-            }
-        }
-        {
-            RowQ<C> q[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) q[k] = row_q(sm.uy + corner + k * RW);
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                v[n] = q[n + 2].h0;
-                div[n] = div[n] + grad_y(q + n);
-            }
-        }
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-            if ((hj >> n) & 1u) continue;  // a solid node: its coefficients stay zero
-            const C ir = Ar<C>::rcp(rho[n]);
-            // (1/(rho cv)) div(lambda grad T) with lambda = rho cv alpha(rho):
-            //   alpha (lap T + grad rho . grad T / rho) + alpha'(rho) grad rho . grad T
-            C dal;
-            const C al = alpha_at<PH>(R, K, rho[n], dal);
-            const C gcoef = al * ir + dal;
-            const C gx = gcoef * gxr[n];
-            const C gy = gcoef * gyr[n];
-            const C D = div[n] * ir * K.inv_cv;
-            const C d1 = (C)1 - K.b * rho[n];
-            const C d2 = (C)1 + (C)2 * K.b * rho[n] - K.b * K.b * rho[n] * rho[n];
-            const C A2 = D * K.a * rho[n] * rho[n] * Ar<C>::rcp(d2);
-            const C c1 = -D * rho[n] * K.Rg * Ar<C>::rcp(d1) + K.dphi_B * A2;
-            f.c2[n] = K.dphi_A * A2;
-            // third-order upwind-biased convection per axis:
-            //   u (8 d1 - d2) / 12 + |u| c_d (S2 - 4 S1 + 6 Y)   (d, S: differences / sums of the pair)
-            const C au = absval(u[n]) * cd, av = absval(v[n]) * cd;
-            f.gx[n] = gx;
-            f.gy[n] = gy;
-            if constexpr (PH) f.al[n] = al;
-            f.u12[n] = u[n] * (C)(1.0 / 12.0);
-            f.v12[n] = v[n] * (C)(1.0 / 12.0);
-            f.au[n] = au;
-            f.av[n] = av;
-            f.c0[n] = c1 - (C)(2 * WSUM) * al - (C)6 * (au + av);
-        }
+        thermal_coef<C, PH>(R, K, rr, ru, rv, hj, cd, f);
         // (T^n, the stage-1 input, is not written before the barrier that follows)
         if (last_s1) {
             Th::rhs(sm.Y, K, tmp, c, phase, S.k1);
@@ -959,6 +989,208 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
                 *at<C>(R.T[pt ^ 1], (unsigned)((gy + n) * P + gx)) =
                     ((S.hold >> (2 * j + n)) & 1u) ? K.T_w
                                                    : (Th::RK_IN_LDS ? sm.uy[S.own(j) + n * RW] : S.acc[Th::RK_IN_LDS ? 0 : j][n]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// k_thermal_strip: the temperature step of a column strip, marching down a chunk of rows
+// ------------------------------------------------------------------------------------------
+// Lane l owns column x0 - 8 + l: the strip's W = NT - 16 columns and an 8-column halo on either
+// side.  Iteration i brings rows 2i, 2i+1 of the frozen fields and T^n (counted from 2 NS rows above
+// the chunk) into rings of 8 rows in LDS and issues the loads of the next two.  The stage-invariant
+// coefficients and stage 1 of a pair of rows follow two rows behind the rows brought in, stage s + 1
+// two rows behind stage s, so stage NS finishes the pair 2 NS rows behind them.  Stage s evaluates
+// the chunk grown by 2 (NS - s) rows at either end and the strip grown by as many columns: the halo
+// is paid on two sides of a long strip instead of all four sides of a tile.  A pair keeps its
+// coefficients, T^n and Runge-Kutta accumulator in registers from its stage 1 to its stage NS (NS
+// sets in rotation); the loop is unrolled by the rings' period of four pairs, which fixes every ring
+// slot and register set at compile time.  The arithmetic of a position is k_thermal's (thermal_coef,
+// thermal_rhs, the same Runge-Kutta updates), so the results are the same bit for bit.
+template <int NS, int NT> struct ThStrip {
+    static_assert(NS == 2 || NS == 4, "RK2 or RK4");
+    static constexpr int HX = 8, W = NT - 2 * HX, HY = 2 * NS;
+    static constexpr int NA = 3 + NS;  // rings: rho, u_x, u_y, then the NS stage inputs
+    static constexpr int RS = 8 * NT;  // values of one ring
+};
+
+// (the tile entry: strip tx, the chunk's first row ty and its row count pad, a multiple of 8, so that
+// the march takes a whole number of ring periods)
+template <typename C, int NS, int NT, bool PH, int OCC = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void k_thermal_strip(
+    const RunDev *__restrict__ runs, const Tile *__restrict__ tiles, int pt, long long step)
+{
+    static_assert(!is_dual<C>, "the tangent precision takes k_thermal_tan");
+    using G = ThStrip<NS, NT>;
+    constexpr int HX = G::HX, W = G::W, HY = G::HY, RS = G::RS;
+    // the rings, with two guard values at either end: the windows of the two outermost lanes on each
+    // side, which lie outside every stage, reach two columns past their rows
+    __shared__ C ring[G::NA * RS + 4];
+
+    const Tile t = tiles[blockIdx.x];
+    const RunDev &R = runs[t.run];
+    const int x0 = t.tx * W, y0 = t.ty, CH = t.pad;
+    const int NI = CH / 2 + 2 * NS;  // iterations, a multiple of 4
+    const int nx = R.nx, ny = R.ny, P = R.pitch;
+    const int lane = threadIdx.x;
+    const int gx = x0 - HX + lane;
+    if (step < R.warmup || R.rk == 0) {
+        // this run does not advance its temperature in this step: carry T over
+        if (lane >= HX && lane < NT - HX && gx < nx) {
+            const gp<const C> Tin = gin<C>(R.T[pt]);
+            const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
+            for (int y = y0; y < min(y0 + CH, ny); ++y) Tout[(size_t)y * P + gx] = Tin[(size_t)y * P + gx];
+        }
+        return;
+    }
+    const Consts<C> K(R);
+    const C cd = R.upwind_kind == 1 ? (C)0.25 : (C)(1.0 / 12.0);
+    const bool phase = PH && R.phase_props;
+
+    // the lane's column: its kind, the domain column it reads and the lane the operator is evaluated
+    // at (for an outlet ghost, the last domain column's); inlet and wall ghosts hold their values
+    int rx, ry_unused;
+    const int kind = map_pos<PH>(R, gx, 0, rx, ry_unused);
+    const int ev = kind == OUTLET_GHOST ? (nx - 1) - (x0 - HX) : lane;
+    const bool ghost = kind == INLET_GHOST || kind == WALL_GHOST;
+    const bool inlet = kind == INLET_GHOST, wall = PH && kind == WALL_GHOST;
+    // rows of the march; a chunk whose region lies inside the domain and misses the cylinder's box
+    // needs no solid test
+    const int ry0 = y0 - HY, ry1 = y0 + CH + HY;
+    const bool no_solid =
+        R.cyl_r <= 0 || (x0 - HX >= 0 && x0 + W + HX <= nx && ry0 >= 0 && ry1 <= ny &&
+                         (x0 + W + HX <= R.cyl_x - R.cyl_r || x0 - HX > R.cyl_x + R.cyl_r ||
+                          ry1 <= R.cyl_y - R.cyl_r || ry0 > R.cyl_y + R.cyl_r));
+
+    C *const own = ring + 2 + lane;          // the lane's column of ring 0, row slot 0
+    const C *const win = ring + ev;          // column -2 of the lane's windows, ring 0, row slot 0
+    const gp<C> Tout = gout<C>(R.T[pt ^ 1]);
+
+    // rows 2i, 2i+1 of the march, in flight between iterations
+    C lr[2], lu[2], lv[2], lt[2];
+    auto load = [&](int i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const unsigned idx = (unsigned)(wrap(ry0 + 2 * i + j, ny) * P + rx);
+            lr[j] = ld_at<C>(R.rho, idx);
+            lu[j] = ld_at<C>(R.ux, idx);
+            lv[j] = ld_at<C>(R.uy, idx);
+            lt[j] = ld_at<C>(R.T[pt], idx);
+        }
+    };
+    // per pair in flight (set p & 3 for pair p): coefficients, T^n, accumulators, held nodes
+    ThCoef<C, PH> cf[4];
+    C T0[4][2], acc[4][2];
+    unsigned hold[4];
+
+    // the window rows -2 .. 3 of the pair starting at ring row slot `top` of ring a
+    auto window = [&](int a, int top, const C *rows[6]) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) rows[r] = win + a * RS + ((top - 2 + r) & 7) * NT;
+    };
+    // k of stage s of the pair in set p whose rows start at slot `top` (held nodes: k = 0)
+    auto stage_k = [&](int s, int p, int top, C k[2]) {
+        const C *rows[6];
+        window(2 + s, top, rows);
+        thermal_rhs<C, PH>(rows, K, cf[p], phase, k);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) k[n] = ((hold[p] >> n) & 1u) ? (C)0 : k[n];
+    };
+    auto store = [&](int p, int row) {
+        if (lane < HX || lane >= NT - HX || gx >= nx) return;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int gy = ry0 + row + n;
+            if (gy < ny) Tout[(size_t)gy * P + gx] = ((hold[p] >> n) & 1u) ? K.T_w : acc[p][n];
+        }
+    };
+
+    auto iteration = [&](auto UU, int m) {
+        constexpr int U = decltype(UU)::value;
+        const int i = 4 * m + U;
+        // rows 2i, 2i+1 into ring slots 2U, 2U+1 (ghost values replace the loaded ones)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            C *o = own + (2 * U + j) * NT;
+            o[0] = wall ? K.rho_w : lr[j];
+            o[RS] = wall ? (C)0 : lu[j];
+            o[2 * RS] = wall ? (C)0 : lv[j];
+            o[3 * RS] = inlet ? K.T_sat : (wall ? K.T_w : lt[j]);
+        }
+        if (i + 1 < NI) load(i + 1);
+        __syncthreads();
+        // pair i - 1 (rows 2i-2, 2i-1 at slots 2U-2, 2U-1): its coefficients, then stage 1
+        if (i >= 2) {
+            constexpr int p = (U + 3) & 3, top = (2 * U - 2) & 7;
+            unsigned hj = ghost ? 3u : 0u;
+            if (!no_solid && !ghost) {
+                const int ya = wrap(ry0 + 2 * i - 2, ny), yb = ya + 1 == ny ? 0 : ya + 1;
+                hj = (solid_at(R, rx, ya) ? 1u : 0u) | (solid_at(R, rx, yb) ? 2u : 0u);
+            }
+            hold[p] = hj;
+            const C *rr[6], *ru[6], *rv[6];
+            window(0, top, rr);
+            window(1, top, ru);
+            window(2, top, rv);
+            thermal_coef<C, PH>(R, K, rr, ru, rv, 0u, cd, cf[p]);
+            C k[2];
+            stage_k(1, p, top, k);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const C t0 = own[3 * RS + ((top + n) & 7) * NT];
+                T0[p][n] = t0;
+                acc[p][n] = k[n];
+                own[4 * RS + ((top + n) & 7) * NT] = NS == 4 ? t0 + (C)0.5 * k[n] : t0 + k[n];
+            }
+        }
+        __syncthreads();
+        // pair i - 2: stage 2
+        if (i >= 4) {
+            constexpr int p = (U + 2) & 3, top = (2 * U - 4) & 7;
+            C k[2];
+            stage_k(2, p, top, k);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                if constexpr (NS == 4) {
+                    acc[p][n] += (C)2 * k[n];
+                    own[5 * RS + ((top + n) & 7) * NT] = T0[p][n] + (C)0.5 * k[n];
+                } else {
+                    acc[p][n] = T0[p][n] + (C)0.5 * (acc[p][n] + k[n]);
+                }
+            }
+            if constexpr (NS == 2) store(p, 2 * i - 4);
+        }
+        if constexpr (NS == 4) {
+            __syncthreads();
+            // pair i - 3: stage 3
+            if (i >= 6) {
+                constexpr int p = (U + 1) & 3, top = (2 * U - 6) & 7;
+                C k[2];
+                stage_k(3, p, top, k);
+#pragma unroll
+                for (int n = 0; n < 2; ++n) {
+                    acc[p][n] += (C)2 * k[n];
+                    own[6 * RS + ((top + n) & 7) * NT] = T0[p][n] + k[n];
+                }
+            }
+            __syncthreads();
+            // pair i - 4: stage 4 and the new temperature
+            if (i >= 8) {
+                constexpr int p = U & 3, top = (2 * U - 8) & 7;
+                C k[2];
+                stage_k(4, p, top, k);
+#pragma unroll
+                for (int n = 0; n < 2; ++n) acc[p][n] = T0[p][n] + (acc[p][n] + k[n]) * (C)(1.0 / 6.0);
+                store(p, 2 * i - 8);
+            }
+        }
+    };
+
+    load(0);
+    for (int m = 0; m < NI / 4; ++m) {
+        iteration(std::integral_constant<int, 0>{}, m);
+        iteration(std::integral_constant<int, 1>{}, m);
+        iteration(std::integral_constant<int, 2>{}, m);
+        iteration(std::integral_constant<int, 3>{}, m);
     }
 }
 
@@ -1427,8 +1659,11 @@ static const Variant kLbm64[] = {{32, 16, 256, 0}, {16, 16, 256, 0}};
 // temperature update (LDS holds 4 fields of the tile grown by 2 nodes per stage); 64 x 32 with 512
 // threads also with a register budget of 4 waves per SIMD, which gives it a second workgroup per CU
 static const Variant kTh32[] = {{64, 32, 512, 0}, {32, 32, 512, 0}, {64, 32, 1024, 0}, {32, 32, 256, 0},
-                                {64, 32, 512, 4}};
-static const Variant kTh64[] = {{16, 16, 256, 0}, {32, 16, 256, 0}};
+                                {64, 32, 512, 4},
+                                // strips of NT - 16 columns marching down chunks of rows: 64 rows, and
+                                // chunks that spread the strips over the resident workgroups
+                                {240, 64, 256, 2, 1}, {240, 0, 256, 2, 1}, {112, 0, 128, 2, 1}};
+static const Variant kTh64[] = {{16, 16, 256, 0}, {32, 16, 256, 0}, {112, 64, 128, 2, 1}, {112, 0, 128, 2, 1}};
 // tangent precision (40-byte values): one small tile each (the RK4 temperature tile with its
 // 8-node halo stays within the 160 KB of LDS)
 static const Variant kTanLbm[] = {{16, 16, 256, 0}};
@@ -1438,12 +1673,13 @@ int variant_count(int precision, int kernel)
 {
     if (precision == 4) return 1;
     if (kernel == 0) return precision == 0 ? 2 : 11;
-    return precision == 0 ? 2 : 5;
+    return precision == 0 ? 4 : 8;
 }
+
 
 Variant variant_shape(int precision, int kernel, int v)
 {
-    if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0, 0};
+    if (v < 0 || v >= variant_count(precision, kernel)) return Variant{0, 0, 0, 0, 0};
     if (precision == 4) return kernel == 0 ? kTanLbm[v] : kTanTh[v];
     if (kernel == 0) return precision == 0 ? kLbm64[v] : kLbm32[v];
     return precision == 0 ? kTh64[v] : kTh32[v];
@@ -1568,6 +1804,37 @@ static hipError_t th_go(int rk, bool phase, const RunDev *runs, const Tile *tile
     return hipGetLastError();
 }
 
+// the strip kernel of an RK order and launch kind
+template <typename C, int NT, int OCC>
+static const void *th_strip_fn(int rk, bool phase)
+{
+    if (phase) {
+        if (rk == 4) return (const void *)k_thermal_strip<C, 4, NT, true, OCC>;
+        if (rk == 2) return (const void *)k_thermal_strip<C, 2, NT, true, OCC>;
+    } else {
+        if (rk == 4) return (const void *)k_thermal_strip<C, 4, NT, false, OCC>;
+        if (rk == 2) return (const void *)k_thermal_strip<C, 2, NT, false, OCC>;
+    }
+    return nullptr;
+}
+
+template <typename C, int NT, int OCC = 0>
+static hipError_t th_strip_go(int rk, bool phase, const RunDev *runs, const Tile *tiles, int n, int pt, long long step,
+                              hipStream_t st, const Timing *tm)
+{
+    static_assert(!is_dual<C>, "strips are built for the plain precisions");
+    if (phase) {
+        if (rk == 4) dispatch(k_thermal_strip<C, 4, NT, true, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else if (rk == 2) dispatch(k_thermal_strip<C, 2, NT, true, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else return hipErrorInvalidValue;
+    } else {
+        if (rk == 4) dispatch(k_thermal_strip<C, 4, NT, false, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else if (rk == 2) dispatch(k_thermal_strip<C, 2, NT, false, OCC>, n, NT, st, tm, runs, tiles, pt, step);
+        else return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const RunDev *runs_dev, const Tile *tiles,
                           int n_tiles, int pt, long long step, hipStream_t stream, const Timing *timing)
 {
@@ -1580,6 +1847,8 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
         switch (variant) {
         case 0: return th_go<double, 16, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
         case 1: return th_go<double, 32, 16, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+        case 2: return th_strip_go<double, 128, 2>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+        case 3: return th_strip_go<double, 128, 2>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1589,8 +1858,24 @@ hipError_t launch_thermal(int precision, int rk, int variant, bool phase, const 
     case 2: return th_go<float, 64, 32, 1024>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     case 3: return th_go<float, 32, 32, 256>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     case 4: return th_go<float, 64, 32, 512, 4>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 5: return th_strip_go<float, 256, 2>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 6: return th_strip_go<float, 256, 2>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
+    case 7: return th_strip_go<float, 128, 2>(rk, phase, runs_dev, tiles, n_tiles, pt, step, stream, timing);
     default: return hipErrorInvalidValue;
     }
+}
+
+int chunked_blocks_per_cu(int precision, int variant, int rk, bool phase)
+{
+    if (precision == 4 || !variant_shape(precision, 1, variant).chunked) return 0;
+    const Variant v = variant_shape(precision, 1, variant);
+    const void *fn = nullptr;
+    if (precision == 0) fn = th_strip_fn<double, 128, 2>(rk, phase);
+    else if (v.nt == 256) fn = th_strip_fn<float, 256, 2>(rk, phase);
+    else fn = th_strip_fn<float, 128, 2>(rk, phase);
+    int b = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, v.nt, 0) != hipSuccess) return 0;
+    return b;
 }
 
 hipError_t launch_diag(int precision, const RunDev *runs_dev, const DiagBlock *blocks, int n_blocks, int run0, int n_runs,

@@ -443,6 +443,46 @@ def test_stream_collide_variants_agree_several_strips(lbm_mod, case):
             assert all(np.array_equal(x, y) for x, y in zip(st, ref_state)), (case, vl)
 
 
+@pytest.mark.parametrize("case", ["channel", "periodic", "warmup", "wall", "rk2"])
+def test_temperature_variants_agree_several_strips(lbm_mod, case):
+    """Every launch variant of the temperature kernel (tiles, and strips marching down chunks of rows)
+    gives the same state bit for bit on grids that take several strips and chunks with ragged last
+    ones: a heated-cylinder channel whose cylinder spans two chunks, a periodic box with random
+    fields, a warm-up that ends mid-run, a heated wall with phase-dependent transport, and RK2 with
+    the Kawamura-Kuwahara upwind weight."""
+    from paper_1912_02018_amd.config import BC_WALL_OUTLET, OUTLET_LOCAL
+    rl, rv = coex()
+    fields = None
+    if case == "channel":
+        cfg = cylinder_case(nx=600, ny=150, r=12, cx=250, precision=FP32).replace(cyl_y=64)
+    elif case == "periodic":
+        cfg = LBMConfig(nx=270, ny=133, bc_x=BC_PERIODIC, rk_stages=4, nu=0.05, alpha_T=0.02, dTr_wall=0.05,
+                        rho_l=rl, rho_v=rv, precision=FP32, gy=-1e-5)
+        fields = inputs.random_fields(270, 133, rl, 0.05, 0.01, seed=9)
+    elif case == "warmup":
+        cfg = cylinder_case(nx=500, ny=140, r=10, cx=70, precision=FP32, warmup_steps=25)
+    elif case == "wall":
+        cfg = LBMConfig(nx=300, ny=70, bc_x=BC_WALL_OUTLET, rk_stages=4, nu=0.05, nu_vapor=0.15, alpha_T=0.01,
+                        alpha_vapor=0.1, rho_l=rl, rho_v=rv, rho_wall=rv, dTr_wall=0.09, precision=FP32,
+                        outlet_kind=OUTLET_LOCAL)
+        fields = (inputs.slab(300, 70, 20, 300, rl, rv), np.zeros((70, 300)), np.zeros((70, 300)))
+    else:
+        cfg = cylinder_case(nx=520, ny=150, r=10, cx=120, rk=2, upwind_kind=1, precision=FP32)
+    ref_state = None
+    nt = len(lbm_mod.Simulation(cfg).variants(1))
+    for vt in range(nt):
+        sim = lbm_mod.Simulation(cfg)
+        if fields is not None:
+            sim.set_fields(*fields)
+        sim.set_variant(1, vt)
+        sim.step(60)
+        st = sim.get_state()[:3]
+        if ref_state is None:
+            ref_state = st
+        else:
+            assert all(np.array_equal(x, y) for x, y in zip(st, ref_state)), (case, vt)
+
+
 def test_autotune_cache(lbm_mod):
     """A tuned choice is remembered per workload shape: cached=True on another handle of the same
     shape applies it without timing; a new shape is tuned on its first cached call."""
