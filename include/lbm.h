@@ -289,8 +289,9 @@ int lbm_set_option(lbm_handle *h, int option, int value);
  * lbm_step splits the runs into G contiguous ranges of about equal node counts and steps each range
  * on a private stream of its own (default priority), forked from and joined back to the handle's
  * stream by events, so that one range's temperature update runs beside another range's streaming.
- * Launches are then direct (no graph replay).  Each run sees the same launches in the same order as
- * with one stream, so results are bitwise the same.  Setting the option waits for the handle's
+ * With LBM_OPT_GRAPHS the window of steps, fork and join included, is captured into one HIP graph
+ * whose groups are parallel branches, and replayed on the handle's stream.  Each run sees the same
+ * launches in the same order as with one stream, so results are bitwise the same.  Setting the option waits for the handle's
  * stream.  lbm_get_option returns the current value (-1 for an unknown option or a NULL handle);
  * lbm_stream_group_runs gives the runs [run0, run1) of group `group` (LBM_EINVAL if out of range). */
 #define LBM_MAX_STREAM_GROUPS 8

@@ -26,6 +26,7 @@ using lbm::Tile;
 // A captured window of steps, replayed while the launch pattern repeats.
 struct StepGraph {
     int pf, pt, ph, length;
+    int groups;  // stream groups the window was captured with (0: one stream)
     long long phase;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -940,42 +941,53 @@ int lbm_step(lbm_handle *h, int n_steps)
         max_warm = std::max(max_warm, h->cfgs[r].warmup_steps);
     }
     const long long L = pattern_length(h);
+    const int ng = (int)h->groups.size();
     long long remaining = n_steps;
-    if (!h->groups.empty() && n_steps > 0) {
-        // fork from the caller's stream, step every group on its own stream, join back
+    // k steps by direct launches: on the caller's stream, or forked from it onto the group streams
+    // (every group's runs stepped on its own stream) and joined back
+    auto eager_steps = [&](long long k) -> int {
+        if (ng == 0) {
+            for (long long j = 0; j < k; ++j)
+                if (int rc = enqueue_step(h)) return rc;
+            return LBM_OK;
+        }
         HIPCHK(h, hipEventRecord(h->fork, h->stream));
         for (const auto &g : h->groups) HIPCHK(h, hipStreamWaitEvent(g.s, h->fork, 0));
-        for (long long k = 0; k < remaining; ++k) {
-            int rc = enqueue_step_groups(h);
-            if (rc) return rc;
-        }
+        for (long long j = 0; j < k; ++j)
+            if (int rc = enqueue_step_groups(h)) return rc;
         for (const auto &g : h->groups) {
             HIPCHK(h, hipEventRecord(g.done, g.s));
             HIPCHK(h, hipStreamWaitEvent(h->stream, g.done, 0));
         }
-        remaining = 0;
-    }
+        return LBM_OK;
+    };
     while (remaining > 0) {
         // replay a captured window when the pattern repeats (all runs past warm-up, window aligned)
         const bool periodic = h->step >= max_warm;
         if (h->use_graphs && periodic && L <= 4096 && remaining >= L && h->step % L == 0) {
             StepGraph *g = nullptr;
             for (auto &c : h->graphs)
-                if (c.pf == h->pf && c.pt == h->pt && c.ph == h->ph && c.length == (int)L) g = &c;
+                if (c.pf == h->pf && c.pt == h->pt && c.ph == h->ph && c.length == (int)L && c.groups == ng) g = &c;
             if (!g) {
-                StepGraph c{h->pf, h->pt, h->ph, (int)L, h->step, nullptr, nullptr};
+                StepGraph c{h->pf, h->pt, h->ph, (int)L, ng, h->step, nullptr, nullptr};
                 const int pf = h->pf, pt = h->pt, ph = h->ph;
                 const long long st = h->step;
                 // record on a private stream (the caller's may be the legacy default stream, which
-                // cannot be captured); the graph is launched on the caller's stream
+                // cannot be captured); the graph is launched on the caller's stream.  With stream
+                // groups the fork and join events bring the group streams into the capture, so the
+                // groups become parallel branches of the graph.
                 if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
                 hipStream_t user = h->stream;
                 h->stream = h->cap_stream;
                 hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
                 int rc = LBM_OK;
                 if (e == hipSuccess) {
-                    for (long long k = 0; k < L && rc == LBM_OK; ++k) rc = enqueue_step(h);
-                    e = hipStreamEndCapture(h->stream, &c.graph);
+                    rc = eager_steps(L);
+                    hipGraph_t graph = nullptr;
+                    const hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+                    c.graph = graph;
+                    e = rc == LBM_OK ? e2 : hipSuccess;
+                    if (rc != LBM_OK && graph) (void)hipGraphDestroy(graph);
                 }
                 h->stream = user;
                 // the capture only recorded work: restore the counters it advanced
@@ -996,14 +1008,11 @@ int lbm_step(lbm_handle *h, int n_steps)
             remaining -= reps * L;
             continue;
         }
-        // eager steps until the window is aligned (or without graphs)
+        // direct launches until the window is aligned (or without graphs)
         long long eager = remaining;
         if (h->use_graphs && periodic) eager = std::min(eager, L - h->step % L);
         else if (h->use_graphs && !periodic) eager = std::min(eager, (long long)max_warm - h->step);
-        for (long long k = 0; k < eager; ++k) {
-            int rc = enqueue_step(h);
-            if (rc) return rc;
-        }
+        if (int rc = eager_steps(eager)) return rc;
         remaining -= eager;
     }
     if (any_check) {
@@ -1534,6 +1543,7 @@ int lbm_set_option(lbm_handle *h, int option, int value)
                         h->n_runs);
         HIPCHK(h, hipStreamSynchronize(h->stream));
         drop_groups(h);
+        drop_graphs(h);  // windows captured with the former groups
         if (value == 1) return LBM_OK;
         // contiguous ranges of runs with about equal node counts
         std::vector<double> cum(h->n_runs + 1, 0.0);

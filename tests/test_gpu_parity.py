@@ -598,6 +598,28 @@ def test_checkpoint_resume_bitwise(lbm_mod, pname):
         wrong.load(blob)
 
 
+def test_stream_groups_graph_replay_bitwise(lbm_mod):
+    """Stream groups captured into one graph per window (fork, the groups' launches as parallel
+    branches, join) and replayed many times, with direct launches, reads and synchronisation between
+    the calls: every read equals the same runs stepped on one stream without graphs."""
+    cfgs = [cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32, warmup_steps=12, diag_every=5),
+            cylinder_case(nx=130, ny=70, r=8, cx=40, precision=FP32, dTr_wall=0.2, diag_every=5),
+            cylinder_case(nx=64, ny=40, r=5, cx=20, precision=FP32, diag_every=10),
+            cylinder_case(nx=160, ny=64, r=6, cx=40, precision=FP32, diag_every=5)]
+    ref = lbm_mod.Simulation(cfgs)
+    ref.set_graphs(False)
+    sim = lbm_mod.Simulation(cfgs)
+    sim.set_stream_groups(3)
+    for n in (7, 40, 13, 60, 20, 3, 57):
+        ref.step(n)
+        sim.step(n)
+        for r in range(len(cfgs)):
+            assert all(np.array_equal(x, y) for x, y in zip(sim.get_state(r)[:3], ref.get_state(r)[:3])), (n, r)
+            assert sim.wall_heat_flux(r) == ref.wall_heat_flux(r), (n, r)
+    sim.close()
+    ref.close()
+
+
 def test_stream_groups_bitwise(lbm_mod):
     """Runs stepped as stream groups (contiguous ranges of runs on streams of their own) end in the
     same states, fields and heat fluxes as the same handle on one stream, through warm-ups that end at
