@@ -1117,6 +1117,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
             o[3 * RS] = inlet ? K.T_sat : (wall ? K.T_w : lt[j]);
         }
         if (i + 1 < NI) load(i + 1);
+        // the new temperatures of the pair that finished its last stage in the previous iteration,
+        // stored only now: they follow the loads just issued, so the next iteration's wait for those
+        // loads does not wait for these stores as well (the counter of outstanding vector memory
+        // operations drains in issue order)
+        if (i >= 2 * NS + 1) store((U + 3 - NS) & 3, 2 * (i - NS - 1));
         __syncthreads();
         // pair i - 1 (rows 2i-2, 2i-1 at slots 2U-2, 2U-1): its coefficients, then stage 1
         if (i >= 2) {
@@ -1157,7 +1162,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
                     acc[p][n] = T0[p][n] + (C)0.5 * (acc[p][n] + k[n]);
                 }
             }
-            if constexpr (NS == 2) store(p, 2 * i - 4);
         }
         if constexpr (NS == 4) {
             __syncthreads();
@@ -1180,7 +1184,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
                 stage_k(4, p, top, k);
 #pragma unroll
                 for (int n = 0; n < 2; ++n) acc[p][n] = T0[p][n] + (acc[p][n] + k[n]) * (C)(1.0 / 6.0);
-                store(p, 2 * i - 8);
             }
         }
     };
@@ -1192,6 +1195,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OC
         iteration(std::integral_constant<int, 2>{}, m);
         iteration(std::integral_constant<int, 3>{}, m);
     }
+    // the last pair (pair NI - 1 - NS, whose set is (NI - 1 - NS) mod 4 with NI a multiple of 4)
+    store((3 - NS) & 3, 2 * (NI - 1 - NS));
 }
 
 // k_thermal_tan: the same temperature step in the tangent precision, one position per slot (the
