@@ -214,7 +214,7 @@ def reduced_storage_report(lbm, steps=1000):
         if rho_l is None:
             rho_l = sim.derived()["rho_l"]
         sim.step(cfg.warmup_steps)
-        sim.autotune(10)
+        tune(sim, 10)
         ms, _ = timed_steps(torch, sim, steps)
         f = sim.fields()
         _, nu, _ = sim.wall_heat_flux()
@@ -315,7 +315,7 @@ def _hbm_resident(lbm, prec, steps, rk=4, copy_gbs=None):
         cfg = cfg.replace(rho_ref_shift=lbm.saturation(cfg)["rho_l"])
     sim = lbm.Simulation(cfg)
     sim.step(10)
-    sim.autotune(5)
+    tune(sim, 5)
     sim.step(10)
     ms, _ = timed_steps(torch, sim, steps)
     nodes = cfg.nx * cfg.ny
@@ -335,13 +335,23 @@ def _hbm_resident(lbm, prec, steps, rk=4, copy_gbs=None):
     return rec
 
 
+def tune(sim, launches, cached=False):
+    """The library's autotuner timing whole steps (the state advances through them, as the untimed
+    steps before a timed region do): pseudo-steps on an unchanged state see other cache contents than
+    stepping, which alternates the double buffers.  Returns the chosen variants."""
+    sim.set_tune_steps(True)
+    best = sim.autotune(launches, cached=cached)
+    sim.set_tune_steps(False)
+    return best
+
+
 def choose_variants(args, sim, launches):
     """Given variants (--variants), the defaults (--no-autotune) or the autotuner's choice."""
     if args.variants:
         for k, v in enumerate(int(x) for x in args.variants.split(",")):
             sim.set_variant(k, v)
     elif not args.no_autotune:
-        sim.autotune(launches)
+        tune(sim, launches)
 
 
 def timed_steps(torch, sim, steps):
@@ -482,10 +492,11 @@ def run_single(args, lbm, cfg, prec, workload, re):
     progress(f"{workload}: warm-up")
     sim = lbm.Simulation(cfg)
     sim.step(cfg.warmup_steps)          # physical warm-up of the configuration (untimed)
-    # launch variants timed on the coupled state (untimed); small grids take more pseudo-steps per
-    # variant, which keeps the choice stable against run-to-run noise at little cost
+    # launch variants timed over coupled steps (untimed); small grids take more steps per variant,
+    # which keeps the choice stable against run-to-run noise at little cost
     choose_variants(args, sim, 100 if cfg.nx * cfg.ny <= (1 << 20) else 20)
     sim.step(args.warmup)
+    untimed = sim.step_count
     ms, wall, reps = timed_windows(torch, sim, args.steps, args.repeats, launch_period([cfg]))
     ms_step = ms / args.steps
     nodes = cfg.nx * cfg.ny
@@ -497,7 +508,7 @@ def run_single(args, lbm, cfg, prec, workload, re):
         sys.exit(3)
     line = base_line(args, prec, mlups, ms_step, {
         "workload": workload, "nx": cfg.nx, "ny": cfg.ny, "cyl_r": cfg.cyl_r, "u_in": cfg.u_in, "Re": re,
-        "rk_stages": cfg.rk_stages, "warmup_steps_untimed": cfg.warmup_steps + args.warmup,
+        "rk_stages": cfg.rk_stages, "warmup_steps_untimed": untimed,
         "diag_every": cfg.diag_every, "parallelism": "single-gpu",
         "tiles": {"k_lbm": sim.variants(0)[sim.get_variant(0)], "k_thermal": sim.variants(1)[sim.get_variant(1)]},
         "variants": [sim.get_variant(0), sim.get_variant(1)]})
@@ -536,7 +547,7 @@ def run_sweep(args, lbm, cfgs, prec):
         one = lbm.Simulation(c.replace(warmup_steps=0))
         one.step(20)
         if not args.no_autotune:
-            seq_var[f"{c.nx}x{c.ny}r{c.cyl_r}"] = list(one.autotune(10, cached=True))
+            seq_var[f"{c.nx}x{c.ny}r{c.cyl_r}"] = list(tune(one, 10, cached=True))
         align(one, period)
         t_ms, _ = timed_steps(torch, one, period)
         seq_ms += t_ms / period

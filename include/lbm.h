@@ -282,7 +282,7 @@ int lbm_profile_steps(lbm_handle *h, int n_steps, double *kernel_ms);
 /* Options.  LBM_OPT_GRAPHS (default 1): lbm_step captures one period of its launch pattern
  * (2 steps, or the least common multiple with diag_every / check_every) into a HIP graph once
  * every run is past its warm-up, and replays it; 0 launches every kernel directly. */
-enum { LBM_OPT_GRAPHS = 0, LBM_OPT_STREAM_GROUPS = 1 };
+enum { LBM_OPT_GRAPHS = 0, LBM_OPT_STREAM_GROUPS = 1, LBM_OPT_TUNE_STEPS = 2 };
 int lbm_set_option(lbm_handle *h, int option, int value);
 
 /* LBM_OPT_STREAM_GROUPS (default 1): with G > 1 (1 <= G <= min(LBM_MAX_STREAM_GROUPS, n_runs)),
@@ -295,6 +295,11 @@ int lbm_set_option(lbm_handle *h, int option, int value);
  * stream.  lbm_get_option returns the current value (-1 for an unknown option or a NULL handle);
  * lbm_stream_group_runs gives the runs [run0, run1) of group `group` (LBM_EINVAL if out of range). */
 #define LBM_MAX_STREAM_GROUPS 8
+/* LBM_OPT_TUNE_STEPS (default 0): 1 makes lbm_autotune time whole steps of the handle instead of
+ * pseudo-steps on the unchanged state, so the state advances by the steps it times (per variant of
+ * each kernel, two rounds of launches + 3 steps, directly launched on the handle's stream).  Whole
+ * steps alternate the double buffers as stepping does, and the caches with them: on the 1024x512
+ * channel pseudo-steps rank a stream-and-collide tile first that whole steps find 4 % slower. */
 int lbm_get_option(const lbm_handle *h, int option);
 int lbm_stream_group_runs(const lbm_handle *h, int group, int *run0, int *run1);
 

@@ -51,6 +51,7 @@ struct lbm_handle {
     int pf = 0, pt = 0, ph = 0;
     long long step = 0;
     bool use_graphs = true;
+    bool tune_steps = false;  // LBM_OPT_TUNE_STEPS: lbm_autotune times whole steps
     std::vector<StepGraph> graphs;
     // per run: still in the default state of lbm_create (its initial fields depend on u_in)
     std::vector<char> default_state;
@@ -1489,6 +1490,14 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
         }
     }
     if (launches <= 0) launches = 20;
+    // the launches timed: whole steps of the handle (the state advances), or pseudo-steps that
+    // leave it as it is
+    auto timed = [&](int n) -> int {
+        if (!h->tune_steps) return time_pseudo_steps(h, n);
+        for (int j = 0; j < n; ++j)
+            if (int rc = enqueue_step(h)) return rc;
+        return LBM_OK;
+    };
     EventPool pool;  // released on every return path
     for (int k = 0; k < 2; ++k) {
         hipEvent_t e;
@@ -1506,9 +1515,9 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
             for (int v = 0; v < nv; ++v) {
                 int rc = lbm_set_variant(h, k, v);
                 if (rc) return rc;
-                if ((rc = time_pseudo_steps(h, 3))) return rc;
+                if ((rc = timed(3))) return rc;
                 HIPCHK(h, hipEventRecord(e0, h->stream));
-                if ((rc = time_pseudo_steps(h, launches))) return rc;
+                if ((rc = timed(launches))) return rc;
                 HIPCHK(h, hipEventRecord(e1, h->stream));
                 HIPCHK(h, hipEventSynchronize(e1));
                 float ms = 0;
@@ -1535,6 +1544,11 @@ int lbm_set_option(lbm_handle *h, int option, int value)
     if (option == LBM_OPT_GRAPHS) {
         h->use_graphs = value != 0;
         drop_graphs(h);
+        return LBM_OK;
+    }
+    if (option == LBM_OPT_TUNE_STEPS) {
+        if (value != 0 && value != 1) return fail(h, LBM_EINVAL, "LBM_OPT_TUNE_STEPS takes 0 or 1");
+        h->tune_steps = value != 0;
         return LBM_OK;
     }
     if (option == LBM_OPT_STREAM_GROUPS) {
@@ -1581,6 +1595,7 @@ int lbm_get_option(const lbm_handle *h, int option)
 {
     if (!h) return -1;
     if (option == LBM_OPT_GRAPHS) return h->use_graphs ? 1 : 0;
+    if (option == LBM_OPT_TUNE_STEPS) return h->tune_steps ? 1 : 0;
     if (option == LBM_OPT_STREAM_GROUPS) return h->groups.empty() ? 1 : (int)h->groups.size();
     return -1;
 }

@@ -43,7 +43,7 @@ EXPORTED = [
     "lbm_nu_gradient_bytes", "lbm_nu_gradient",
 ]
 STATIC_WORKSPACE_BYTES = 64 << 20
-OPT_GRAPHS, OPT_STREAM_GROUPS = 0, 1
+OPT_GRAPHS, OPT_STREAM_GROUPS, OPT_TUNE_STEPS = 0, 1, 2
 KERNEL_STREAM_COLLIDE, KERNEL_THERMAL = 0, 1
 
 
@@ -249,6 +249,10 @@ class Simulation:
 
     def set_graphs(self, enabled: bool):
         self._check(self._L.lbm_set_option(self.h, OPT_GRAPHS, 1 if enabled else 0))
+
+    def set_tune_steps(self, enabled: bool):
+        """autotune() times whole steps (advancing the state) instead of pseudo-steps."""
+        self._check(self._L.lbm_set_option(self.h, OPT_TUNE_STEPS, 1 if enabled else 0))
 
     def save(self) -> bytes:
         """Checkpoint of every run (raw device state, accumulators and step counter)."""

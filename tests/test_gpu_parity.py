@@ -499,6 +499,28 @@ def test_autotune_cache(lbm_mod):
     assert c.autotune(cached=True) == got
 
 
+def test_autotune_over_whole_steps_advances_the_state_as_stepping(lbm_mod):
+    """With whole-step tuning the autotuner steps the handle (3 + launches steps per variant and round,
+    two rounds over each kernel's variants); since every variant gives the same state bit for bit,
+    the state then equals that of plain stepping by the same count."""
+    cfg = cylinder_case(nx=96, ny=48, r=6, cx=30, precision=FP32)
+    a = lbm_mod.Simulation(cfg)
+    a.step(5)
+    a.set_tune_steps(True)
+    best = a.autotune(2)
+    nv = len(a.variants(0)) + len(a.variants(1))
+    assert a.step_count == 5 + 2 * (3 + 2) * nv
+    assert (a.get_variant(0), a.get_variant(1)) == best
+    b = lbm_mod.Simulation(cfg)
+    b.step(a.step_count)
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state()[:3], b.get_state()[:3]))
+    assert a.wall_heat_flux() == b.wall_heat_flux()
+    a.set_tune_steps(False)
+    n = a.step_count
+    a.autotune(2)
+    assert a.step_count == n
+
+
 def test_autotune_keeps_results(lbm_mod):
     cfg = cylinder_case(nx=128, ny=64, precision=FP32)
     a, b = lbm_mod.Simulation(cfg), lbm_mod.Simulation(cfg)
