@@ -15,7 +15,7 @@ import math
 from .config import LBMConfig
 
 __all__ = ["groups", "jakob", "bromley", "epstein_hauser", "ito", "correlations", "stefan_beta",
-           "stefan_interface", "plesset_zwick_radius"]
+           "stefan_interface", "plesset_zwick_radius", "cylinder_bubble_beta"]
 
 # constants of the correlations as the paper uses them
 BROMLEY_C = 2.7
@@ -97,3 +97,43 @@ def plesset_zwick_radius(t, alpha_l: float, rho_l: float, rho_v: float, cp_l: fl
     """R(t) = (12 alpha_l / pi)^1/2 rho_l c_p,l dT / (rho_v h_fg) t^1/2: bubble growth in a uniformly
     superheated liquid (Plesset-Zwick)."""
     return math.sqrt(12.0 * alpha_l / math.pi) * rho_l * cp_l * dT / (rho_v * h_fg) * t ** 0.5
+
+
+def cylinder_bubble_beta(ja: float, eps: float) -> float:
+    """Growth constant of a cylindrical (2-D) vapour bubble in a uniformly superheated liquid, from the
+    similarity solution R(t) = 2 beta sqrt(alpha_l t): with eta = r / (2 sqrt(alpha_l t)) and the liquid's
+    radial outflow u = eps R dR/dt / r (eps = 1 - rho_v / rho_l), the liquid temperature obeys
+    T'' + (1/eta + 2 eta - 2 eps beta^2 / eta) T' = 0, so T' is proportional to
+    eta^(2 eps beta^2 - 1) exp(-eta^2); T = T_sat at eta = beta, T -> T_sat + dT far away, and the
+    interface balance rho_v h_fg dR/dt = k dT/dr gives
+        Ja = 2 beta int_beta^inf (s / beta)^(2 eps beta^2 - 1) exp(-(s^2 - beta^2)) ds,
+    Ja = rho_l c_p,l dT / (rho_v h_fg).  The right side increases with beta from 0, so the root is
+    bracketed and bisected.  For eps = 1 and large Ja it tends to the thin-layer law
+    beta = sqrt(2 / pi) Ja, the cylindrical counterpart of Plesset-Zwick's sqrt(3 / pi) Ja."""
+    if ja <= 0.0:
+        return 0.0
+
+    def rhs(beta):
+        p = 2.0 * eps * beta * beta - 1.0
+        # composite Simpson on [beta, beta + L]; the integrand is 1 at s = beta and decays at least
+        # like exp(-(1 + eps) x^2 - 2 beta (1 - eps) x) beyond it
+        L = 12.0 / (1.0 + beta * (1.0 - eps)) + 12.0
+        n = 20000
+        h = L / n
+        tot = 0.0
+        for i in range(n + 1):
+            s = beta + i * h
+            w = 1.0 if i in (0, n) else (4.0 if i % 2 else 2.0)
+            tot += w * math.exp(p * math.log(s / beta) - (s * s - beta * beta))
+        return 2.0 * beta * tot * h / 3.0
+
+    lo, hi = 1e-9, 1.0
+    while rhs(hi) < ja:
+        hi *= 2.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if rhs(mid) < ja:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
