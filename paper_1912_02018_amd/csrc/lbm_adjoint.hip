@@ -48,7 +48,9 @@ enum {
     PTH = PBF + 9,                                     // per-node parameter contributions [4]
     NPLANES = PTH + kTangents
 };
-// after the planes: probe values [kMaxProbes][2], then the probes' parameter contribution [4]
+// after the planes: probe values [kMaxProbes][2], then the probes' parameter contribution [4], then
+// the partial sums of the per-node parameter contributions [kThetaBlocks][4]
+constexpr int kThetaBlocks = 256;
 
 struct AdjArgs {
     const double *fs, *hist, *T;   // state n
@@ -66,6 +68,9 @@ __device__ inline double *PL(const AdjArgs &a, const RunDev &R, int k) { return 
 __device__ inline size_t nid(const RunDev &R, int x, int y) { return (size_t)y * R.pitch + x; }
 __device__ inline double *probe_vals(const AdjArgs &a, const RunDev &R) { return a.ws + (size_t)NPLANES * plane_of(R); }
 __device__ inline double *probe_theta(const AdjArgs &a, const RunDev &R) { return probe_vals(a, R) + 2 * kMaxProbes; }
+__device__ inline double *theta_parts(const AdjArgs &a, const RunDev &R) { return probe_theta(a, R) + kTangents; }
+// workgroups of the parameter-contribution sum: row blocks of about equal height
+__host__ __device__ inline int theta_blocks(int ny) { return ny < kThetaBlocks ? ny : kThetaBlocks; }
 
 // adjoint state layout: lambda_f* [9] planes, lambda_T plane, lambda_hist [3][ny], dJ/dtheta [4]
 __device__ inline size_t adj_T(const RunDev &R) { return 9 * plane_of(R); }
@@ -875,31 +880,55 @@ __global__ __launch_bounds__(256) void kb_stream(const RunDev *__restrict__ runs
     }
 }
 
-// fixed-order sum of the per-node parameter contributions (and the Nu sample's explicit part) onto
-// the incoming accumulated gradient
+// fixed-order tree sum of one value per thread of a 256-thread workgroup (the result in thread 0)
+__device__ inline double tree_sum256(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double s = red[0];
+    __syncthreads();
+    return s;
+}
+
+// the per-node parameter contributions summed over a block of rows per workgroup, in a fixed order
+__global__ __launch_bounds__(256) void kb_theta_part(const RunDev *__restrict__ runs, int run, AdjArgs a)
+{
+    const RunDev &R = runs[run];
+    __shared__ double red[256];
+    const int nb = theta_blocks(R.ny);
+    const int y0 = (int)((long long)blockIdx.x * R.ny / nb), y1 = (int)((long long)(blockIdx.x + 1) * R.ny / nb);
+    double s[kTangents] = {0.0, 0.0, 0.0, 0.0};
+    for (int y = y0; y < y1; ++y)
+        for (int x = threadIdx.x; x < R.nx; x += 256) {
+            const size_t i0 = nid(R, x, y);
+#pragma unroll
+            for (int t = 0; t < kTangents; ++t) s[t] += PL(a, R, PTH + t)[i0];
+        }
+    for (int t = 0; t < kTangents; ++t) {
+        const double v = tree_sum256(s[t], red);
+        if (threadIdx.x == 0) theta_parts(a, R)[(size_t)blockIdx.x * kTangents + t] = v;
+    }
+}
+
+// the row blocks' sums in a fixed order (and the Nu sample's explicit part) onto the incoming
+// accumulated gradient
 __global__ __launch_bounds__(256) void kb_theta(const RunDev *__restrict__ runs, int run, AdjArgs a, int with_probe)
 {
     const RunDev &R = runs[run];
     __shared__ double red[256];
+    const int nb = theta_blocks(R.ny);
     for (int t = 0; t < kTangents; ++t) {
-        const double *th = PL(a, R, PTH + t);
-        double s = 0.0;
-        for (long long k = threadIdx.x; k < (long long)R.nx * R.ny; k += 256) {
-            const int x = (int)(k % R.nx), y = (int)(k / R.nx);
-            s += th[nid(R, x, y)];
-        }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
+        const double v = (int)threadIdx.x < nb ? theta_parts(a, R)[(size_t)threadIdx.x * kTangents + t] : 0.0;
+        const double sum = tree_sum256(v, red);
         if (threadIdx.x == 0) {
-            double tot = a.ain[adj_theta(R) + t] + red[0];
+            double tot = a.ain[adj_theta(R) + t] + sum;
             if (with_probe) tot += probe_theta(a, R)[t];
             a.aout[adj_theta(R) + t] = tot;
         }
-        __syncthreads();
     }
 }
 
@@ -949,7 +978,7 @@ __global__ __launch_bounds__(256) void kb_initial(const RunDev *__restrict__ run
 size_t adjoint_scratch_doubles(int nx, int ny, int pitch)
 {
     (void)nx;
-    return (size_t)NPLANES * ny * pitch + 2 * kMaxProbes + kTangents;
+    return (size_t)NPLANES * ny * pitch + 2 * kMaxProbes + kTangents + (size_t)kThetaBlocks * kTangents;
 }
 
 size_t adjoint_state_doubles(int nx, int ny, int pitch)
@@ -995,6 +1024,7 @@ hipError_t launch_adjoint_step(const RunDev *runs_dev, int run, const RunDev &Rh
     if (fon) go(kb_psi, 0);
     go(kb_bc, 0);
     go(kb_stream, 0);
+    hipLaunchKernelGGL(kb_theta_part, dim3(theta_blocks(Rh.ny)), dim3(256), 0, st, runs_dev, run, a);
     hipLaunchKernelGGL(kb_theta, dim3(1), dim3(256), 0, st, runs_dev, run, a, probe ? 1 : 0);
     return hipGetLastError();
 }
