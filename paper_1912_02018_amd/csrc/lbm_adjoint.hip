@@ -220,8 +220,41 @@ __device__ inline double ext_Y(const RunDev &R, const double *Y, int gx, int gy)
     const int kind = map_pos<false>(R, gx, gy, rx, ry);
     return kind == INLET_GHOST ? R.T_sat : Y[nid(R, rx, ry)];
 }
+// a node whose 5 x 5 window holds no ghost position (x two columns from an inlet or outlet; any x with
+// periodic columns, nx >= 5): its stencil positions and sources are plain offsets (rows wrap)
+__device__ inline bool plain_columns(const RunDev &R, int x) { return R.bc_x == 0 || (x >= 2 && x <= R.nx - 3); }
+__device__ inline int wrap_col(const RunDev &R, int x) { return R.bc_x == 0 ? wrap(x, R.nx) : x; }
 __device__ inline Win window(const RunDev &R, const double *Y, int x, int y)
 {
+    if (plain_columns(R, x)) {
+        // the same sums in the same order, without the ghost mapping of every position
+        Win w{0, 0, 0, 0, 0, 0, 0, 0};
+        w.y0 = Y[nid(R, x, y)];
+        double v[5][5];
+#pragma unroll
+        for (int ey = -2; ey <= 2; ++ey) {
+            const int yy = wrap(y + ey, R.ny);
+#pragma unroll
+            for (int ex = -2; ex <= 2; ++ex) v[ey + 2][ex + 2] = Y[nid(R, wrap_col(R, x + ex), yy)];
+        }
+#pragma unroll
+        for (int ey = -2; ey <= 2; ++ey)
+#pragma unroll
+            for (int ex = -2; ex <= 2; ++ex) {
+                if (ex == 0 && ey == 0) continue;
+                const double yv = v[ey + 2][ex + 2], we = stencil_w(ex, ey);
+                w.lapw += 2.0 * we * yv;
+                w.gx += we * ex * yv;
+                w.gy += we * ey * yv;
+            }
+        const double xp1 = v[2][3], xm1 = v[2][1], xp2 = v[2][4], xm2 = v[2][0];
+        const double yp1 = v[3][2], ym1 = v[1][2], yp2 = v[4][2], ym2 = v[0][2];
+        w.cx1 = 8.0 * (xp1 - xm1) - (xp2 - xm2);
+        w.sx = (xp2 + xm2) - 4.0 * (xp1 + xm1);
+        w.cy1 = 8.0 * (yp1 - ym1) - (yp2 - ym2);
+        w.sy = (yp2 + ym2) - 4.0 * (yp1 + ym1);
+        return w;
+    }
     Win w{0, 0, 0, 0, 0, 0, 0, 0};
     w.y0 = Y[nid(R, x, y)];
     for (int ey = -2; ey <= 2; ++ey)
@@ -497,13 +530,26 @@ __global__ __launch_bounds__(256) void kb_stage(const RunDev *__restrict__ runs,
         PL(a, R, PBLAP)[i0] += k * w.lapw;
     }
     double yb = 0.0;
-    for_sources(R, x, y, false, [&](int sx, int sy, int ex, int ey) {
+    auto source = [&](int sx, int sy, int ex, int ey) {
         if (solid_at(R, sx, sy)) return;
         double c[8];
         const size_t is = nid(R, sx, sy);
         load_coef(a, R, is, c);
         yb += stencil_coef(R.alpha, c, ex, ey) * kb[is];
-    });
+    };
+    if (plain_columns(R, x)) {
+        // the sources t - e in for_sources' order, with compile-time offsets (so that only the
+        // coefficients a source's offset uses are loaded)
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            const int sy = wrap(y + dy, R.ny);
+#pragma unroll
+            for (int dx = -2; dx <= 2; ++dx)
+                if (dx != 0 || dy != 0) source(wrap_col(R, x + dx), sy, -dx, -dy);
+        }
+    } else {
+        for_sources(R, x, y, false, source);
+    }
     if (fluid) {
         double c[8];
         load_coef(a, R, i0, c);
