@@ -256,7 +256,8 @@ int lbm_time_kernel(lbm_handle *h, int kernel, int n_launches);
  * ty = 0 is a strip of tx columns marching down a chunk of rows whose length is chosen when the tile
  * tables are built, so that one launch spreads over the workgroups the GPU holds at once.  lbm_set_variant rebuilds the tile tables
  * (waits for the stream); lbm_autotune times every variant of both kernels on the handle's
- * current state with HIP events (`launches` launches each, 20 if 0) and keeps the fastest, writing
+ * current state with HIP events (`launches` pseudo-steps each, without advancing the state, or whole
+ * steps with LBM_OPT_TUNE_STEPS; 20 if 0) and keeps the fastest, writing
  * the chosen indices to best[2] if not NULL.  Every tuning is remembered for the rest of the process
  * per device and workload shape (precision, RK stages, heated-wall / phase-property launch, and each
  * run's nx, ny, cylinder radius and x boundary); launches < 0 takes the remembered choice for the

@@ -1508,7 +1508,7 @@ int lbm_autotune(lbm_handle *h, int launches, int *best)
     for (int k = 0; k < 2; ++k) {
         if (k == 1 && h->rk == 0) continue;
         // two interleaved rounds over the variants of kernel k (the other kernel at its current
-        // variant), each timed over pseudo-steps; each variant keeps its faster round
+        // variant), each timed over the launches above; each variant keeps its faster round
         const int nv = lbm::variant_count(h->precision, k);
         std::vector<float> t(nv, 1e30f);
         for (int round = 0; round < 2; ++round)
