@@ -9,7 +9,7 @@
 namespace lbm {
 
 constexpr int kMaxProbes = 4096;
-constexpr int kDiagBlocks = 2048;  // most diagnostic workgroups of a run
+constexpr int kDiagBlocks = 1024;  // most diagnostic workgroups of a run
 // parameter directions of the tangent precision: superheat dTr_wall, u_in, acentric factor, tau
 constexpr int kTangents = 4;
 // FP64 accumulators per run: [0] mass, [1] q_mean, [2] Nu, [3] sum of Nu, [4] count, [5] non-finite,

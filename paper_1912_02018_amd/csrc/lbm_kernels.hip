@@ -1529,9 +1529,42 @@ __global__ __launch_bounds__(256) void k_diag_partial(const RunDev *__restrict__
     if (!diag_fires(R, b.run, step, readout, acc)) return;
     __shared__ double lds[4];
     const gp<const C> rho = gin<C>(R.rho);
-    // four row positions per thread and pass, loaded before they are summed (their loads overlap)
     double s = 0.0;
     const int r2 = R.cyl_r * R.cyl_r;
+    constexpr int V = std::is_same<C, float>::value ? 4 : (std::is_same<C, double>::value ? 2 : 1);
+    if constexpr (V > 1) {
+        // 16 bytes (V values) per lane and load, eight loads in flight before they are summed; the
+        // workgroup's rows are contiguous (pitch apart, the pitch a multiple of 64 values, every row
+        // 256-byte aligned), so chunk q of them is row q / nc, columns V (q % nc) on; a chunk past the
+        // last one is loaded clamped and not taken
+        typedef C Vec __attribute__((ext_vector_type(V)));
+        constexpr int U = 8;
+        const int nc = R.pitch / V, nq = (b.row1 - b.row0) * nc;
+        const gp<const Vec> base = (gp<const Vec>)(rho + (size_t)b.row0 * R.pitch);
+        for (int q0 = threadIdx.x; q0 < nq; q0 += 256 * U) {
+            Vec v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) v[j] = base[min(q0 + 256 * j, nq - 1)];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int q = q0 + 256 * j, yr = q / nc, dy = b.row0 + yr - R.cyl_y;
+                const bool in = q < nq, cut = (R.cyl_r > 0) & (dy * dy <= r2);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    // the conditions are combined without short-circuit branches, into one select (the
+                    // branched form lost the value of a taken node next to the cylinder in the FP64
+                    // instantiation built by hipcc 7.2 for gfx950)
+                    const int x = V * (q - yr * nc) + e, dx = x - R.cyl_x;
+                    const bool take = in & (x < R.nx) & !(cut & (dx * dx + dy * dy <= r2));
+                    s += take ? (double)v[j][e] : 0.0;
+                }
+            }
+        }
+        s = block_sum<double>(s, lds);
+        if (threadIdx.x == 0) R.partials[b.index] = s;
+        return;
+    }
+    // four row positions per thread and pass, loaded before they are summed (their loads overlap)
     for (int y = b.row0; y < b.row1; ++y) {
         const gp<const C> row = rho + (size_t)y * R.pitch;
         const int dy = y - R.cyl_y;
