@@ -14,6 +14,10 @@ OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # a multiply and an add are fused only within one source expression: the rounding of every
+    # value is then a property of the source, the same in every kernel that evaluates it (fusing
+    # across statements depends on how often a product is used in the surrounding kernel)
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # the kernel arguments arrive preloaded in scalar registers: one dependent memory round trip

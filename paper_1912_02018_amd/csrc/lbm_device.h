@@ -142,10 +142,20 @@ template <> struct Conv<float> {
     __device__ static float ld(float v, float) { return v; }
     __device__ static float st(float v, float) { return v; }
 };
+// (the shift is added and subtracted as separate roundings, never fused with the product that
+// produced the value: every kernel then stores and loads the same bits)
 template <> struct Conv<__half> {
     using raw = unsigned short;
-    __device__ static float ld(unsigned short v, float s) { return __half2float(__ushort_as_half(v)) + s; }
-    __device__ static unsigned short st(float v, float s) { return __half_as_ushort(__float2half_rn(v - s)); }
+    __device__ static float ld(unsigned short v, float s)
+    {
+#pragma clang fp contract(off)
+        return __half2float(__ushort_as_half(v)) + s;
+    }
+    __device__ static unsigned short st(float v, float s)
+    {
+#pragma clang fp contract(off)
+        return __half_as_ushort(__float2half_rn(v - s));
+    }
 };
 template <> struct Conv<Dual> {
     using raw = Dual;
@@ -154,8 +164,16 @@ template <> struct Conv<Dual> {
 };
 template <> struct Conv<__hip_bfloat16> {
     using raw = unsigned short;
-    __device__ static float ld(unsigned short v, float s) { return __uint_as_float((unsigned)v << 16) + s; }
-    __device__ static unsigned short st(float v, float s) { return __bfloat16_as_ushort(__float2bfloat16(v - s)); }
+    __device__ static float ld(unsigned short v, float s)
+    {
+#pragma clang fp contract(off)
+        return __uint_as_float((unsigned)v << 16) + s;
+    }
+    __device__ static unsigned short st(float v, float s)
+    {
+#pragma clang fp contract(off)
+        return __bfloat16_as_ushort(__float2bfloat16(v - s));
+    }
 };
 template <typename S> using RawT = typename Conv<S>::raw;
 

@@ -406,17 +406,21 @@ def test_launch_variants_agree(lbm_mod, precision, rk):
                 assert all(np.array_equal(x, y) for x, y in zip(st, ref_state)), (vl, vt)
 
 
-@pytest.mark.parametrize("case", ["channel", "periodic", "warmup", "wall"])
+@pytest.mark.parametrize("case", ["channel", "periodic", "warmup", "wall", "f16", "bf16"])
 def test_stream_collide_variants_agree_several_strips(lbm_mod, case):
     """Every launch variant of the stream-and-collide kernel (tiles, and strips marching down chunks of
     rows) gives the same state bit for bit on grids that take several strips and chunks with ragged
-    last ones: a heated-cylinder channel, a periodic box with random fields, a warm-up that ends
-    mid-run, and a heated wall with phase-dependent transport and the local outlet speed."""
+    last ones: a heated-cylinder channel (populations stored in FP32, FP16 and BF16), a periodic box
+    with random fields, a warm-up that ends mid-run, and a heated wall with phase-dependent transport
+    and the local outlet speed."""
     from paper_1912_02018_amd.config import BC_WALL_OUTLET, OUTLET_LOCAL
     rl, rv = coex()
     fields = None
     if case == "channel":
         cfg = cylinder_case(nx=300, ny=150, r=12, cx=90, precision=FP32)
+    elif case in ("f16", "bf16"):
+        from paper_1912_02018_amd.config import FP16S, BF16S
+        cfg = cylinder_case(nx=300, ny=150, r=12, cx=90, precision=FP16S if case == "f16" else BF16S)
     elif case == "periodic":
         cfg = LBMConfig(nx=270, ny=133, bc_x=BC_PERIODIC, rk_stages=4, nu=0.05, alpha_T=0.02, dTr_wall=0.05,
                         rho_l=rl, rho_v=rv, precision=FP32, gy=-1e-5)
@@ -709,3 +713,4 @@ def test_batched_runs_equal_single_runs_bitwise(lbm_mod):
             if same_kernels:
                 assert np.array_equal(fs, fs1), (batch, k)
                 assert q == q1, (batch, k)
+
