@@ -16,7 +16,8 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # a multiply and an add are fused only within one source expression: the rounding of every
     # value is then a property of the source, the same in every kernel that evaluates it (fusing
-    # across statements depends on how often a product is used in the surrounding kernel)
+    # across statements depends on how often a product is used in the surrounding kernel); the
+    # temperature kernels opt back into cross-statement fusion with a pragma
     "-ffp-contract=on",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
