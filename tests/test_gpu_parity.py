@@ -714,3 +714,27 @@ def test_batched_runs_equal_single_runs_bitwise(lbm_mod):
                 assert np.array_equal(fs, fs1), (batch, k)
                 assert q == q1, (batch, k)
 
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_hbm_resident_grid_launch_agrees_with_tiles(lbm_mod, storage):
+    """The 8192x4096 channel (R 256) in the launch the bench times there (the stream-and-collide tile
+    or strip it picks, the temperature strips with chunks sized to the resident workgroups: 35 strips)
+    gives the plain tile variants' state bit for bit after a few coupled steps; the tiles are the ones
+    pinned to the oracle on the smaller grids."""
+    from paper_1912_02018_amd.config import FP16S
+    prec = FP32 if storage == "f32" else FP16S
+    cfg = cylinder_config(8192, 4096, 256, 2048, re=300.0, u_in=0.02, dTr_wall=0.1, precision=prec, warmup=0)
+    if prec == FP16S:
+        cfg = cfg.replace(rho_ref_shift=lbm_mod.saturation(cfg)["rho_l"])
+    states = []
+    for vl, vt in (((6 if storage == "f32" else 10), 6), (3, 0)):
+        sim = lbm_mod.Simulation(cfg)
+        sim.set_variant(0, vl)
+        sim.set_variant(1, vt)
+        sim.step(3)
+        states.append(sim.get_state()[:3])
+        print(f"[full-size] {storage} variants ({vl}, {vt}) stepped", flush=True)
+        sim.close()
+        del sim
+    assert all(np.array_equal(x, y) for x, y in zip(*states))
